@@ -1,0 +1,162 @@
+/*
+ * ridc.h -- C ABI of the MI355X (gfx950) semi-implicit RIDC library.
+ *
+ * Semi-implicit Revisionist Integral Deferred Correction (RIDC-FBE) of Ong, Melfi and
+ * Christlieb, "Parallel Semi-Implicit Time Integrators" (arXiv:1209.4297), for
+ *
+ *     u_t = f_E(u) + f_I(u),     f_I(u) = nu * Lap_h u      (section II, eq. ode; section IV)
+ *
+ * on a uniform finite-difference grid.  Level 0 (the predictor) is first-order IMEX
+ * forward-backward Euler (section II, eq. imex_diffusion; section III-B, eq. pred).  Level
+ * j = 1..P-1 (a corrector) is an IMEX Euler step on the error equation plus the (j+1)-node
+ * Lagrange quadrature of f along level j-1 (section III-C, eq. corr and the quadrature rule that
+ * follows it).  All P levels advance together as the lagged pipeline of section III (Fig. 1):
+ * at pipeline step s level j computes time index s - j(j+1)/2 (the start-up wait of section
+ * III-E), so an integration of nt steps takes nt + P(P-1)/2 pipeline steps.  Every level starts
+ * from u0 (section III-E, Fig. 2).  The result is the top level at t = nt*dt.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status: RIDC_OK (0) or a negative RIDC_E_* code.  No C++
+ *    exception crosses the ABI.  ridc_last_error() gives a message for the calling thread.
+ *  - Arrays are contiguous FP64 in device memory (hipMalloc'd or torch CUDA tensors).  1D: n
+ *    values.  2D: n*n values, row-major u[iy*n + ix].  Dirichlet grids hold the interior
+ *    unknowns only (x_i = i*h, i = 1..n, h = length/(n+1), zero ghosts); periodic grids hold
+ *    x_i = i*h, i = 0..n-1, h = length/n.
+ *  - The caller owns every array it passes; the handle owns its level rings, transform
+ *    matrices, weights and workspaces, and frees them in ridc_destroy.
+ *  - Work is enqueued asynchronously on the HIP stream given to ridc_create (NULL = the null
+ *    stream).  Input arrays must stay valid until the stream reaches the work; the caller
+ *    synchronises (or calls ridc_sync) before reading outputs.
+ *  - Device-side failures (a non-finite result) are reported by ridc_sync.
+ */
+#ifndef RIDC_H
+#define RIDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------------ */
+#define RIDC_OK             0
+#define RIDC_E_INVAL       -1   /* bad argument: n < 2, dt <= 0, order outside 1..12, ...   */
+#define RIDC_E_UNSUPPORTED -2   /* valid but not implemented (e.g. 2D periodic)            */
+#define RIDC_E_NOMEM       -3   /* device allocation failed                                 */
+#define RIDC_E_HIP         -4   /* a HIP runtime call failed                                */
+#define RIDC_E_NONFINITE   -5   /* the result holds a NaN or Inf                            */
+#define RIDC_E_STATE       -6   /* call out of order (e.g. ridc_read before the last step)  */
+
+#define RIDC_MAX_ORDER 12       /* section III-E: orders 8 and 12 are usable in FP64         */
+
+/* ---- problem description ------------------------------------------------------------------ */
+typedef enum { RIDC_BC_PERIODIC = 0, RIDC_BC_DIRICHLET0 = 1 } ridc_bc;
+
+/* Explicit (non-stiff) term f_E, section II: f^N.                                            */
+typedef enum {
+  RIDC_FE_NONE = 0,       /* f_E = 0                                                          */
+  RIDC_FE_ADVECT_C2 = 1,  /* f_E = -a (u_{i+1} - u_{i-1}) / (2h), 1D only                     */
+  RIDC_FE_LOGISTIC = 2    /* f_E = u (1 - u), pointwise                                        */
+} ridc_fe_kind;
+
+/* Arithmetic of the implicit solve.  Quadrature sums and level differences are FP64 always.  */
+typedef enum {
+  RIDC_PREC_FP64 = 0,          /* every operation in FP64                                     */
+  RIDC_PREC_FP32_REFINE = 1,   /* 2D: FP32 MFMA transforms, increment form, one FP64 residual
+                                  refinement                                                  */
+  RIDC_PREC_BF16X3_REFINE = 2  /* 2D: split-BF16 (hi/lo, three products) MFMA transforms with
+                                  FP32 accumulation, increment form, one FP64 refinement      */
+} ridc_prec;
+
+typedef struct {
+  int32_t dim;       /* 1 or 2                                                                */
+  int32_t bc;        /* ridc_bc; 2D supports RIDC_BC_DIRICHLET0 only                          */
+  int64_t n;         /* unknowns per axis, >= 2                                               */
+  double length;     /* domain length per axis, > 0                                           */
+  int32_t fe_kind;   /* ridc_fe_kind                                                           */
+  int32_t order;     /* P = number of levels, 1..RIDC_MAX_ORDER (1 = plain IMEX Euler)        */
+  double a;          /* advection speed (RIDC_FE_ADVECT_C2)                                   */
+  double nu;         /* diffusion coefficient, >= 0; f_I = nu * Lap_h                         */
+  double dt;         /* uniform time step, > 0 (section III-C: one weight table)              */
+  int32_t prec;      /* ridc_prec; 1D always computes in FP64                                 */
+  int32_t reserved;  /* must be 0                                                              */
+} ridc_problem;
+
+typedef struct ridc_handle ridc_handle;   /* opaque; owned by the library                     */
+
+/* ---- lifetime ------------------------------------------------------------------------------ */
+/* Validate *p, build the plan (exact quadrature weights of section III-C, the pipeline schedule,
+ * level rings, solver data) and allocate device memory on the current HIP device.
+ * hip_stream: a hipStream_t (NULL = null stream) on which all later work of the handle runs.
+ * On success *out receives the handle.  Errors: RIDC_E_INVAL, RIDC_E_UNSUPPORTED,
+ * RIDC_E_NOMEM, RIDC_E_HIP.                                                                  */
+int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out);
+
+/* Free everything the handle owns (after synchronising its stream).  NULL-safe.              */
+int ridc_destroy(ridc_handle* h);
+
+/* Device bytes ridc_create would allocate for *p (rings, transforms, workspaces); 0 if *p is
+ * invalid.  Used for admission control by HBM footprint.                                      */
+size_t ridc_footprint_bytes(const ridc_problem* p);
+
+/* ---- one-shot integration ------------------------------------------------------------------ */
+/* Integrate from u0_dev for nsteps uniform steps (t = nsteps*dt): ridc_begin, all pipeline
+ * steps, ridc_read.  nsteps == 0 returns u0; otherwise nsteps >= order-1 is required (the
+ * start-up quadrature of the top corrector uses t_0..t_{P-1}).  uT_dev receives the top level;
+ * levels_dev (nullable) receives every level's final value, level-major (P blocks).
+ * u0_dev and uT_dev may be the same array.  Asynchronous; see ridc_sync.                      */
+int ridc_integrate(ridc_handle* h, const double* u0_dev, int64_t nsteps, double* uT_dev,
+                   double* levels_dev);
+
+/* Integrate `count` handles (any mix of sizes, orders, dims and precisions, all created on the
+ * same stream) together: each pipeline step of every handle is grouped into shared launches.
+ * u0[i], uT[i] and nsteps[i] as in ridc_integrate.  Each handle's result is bitwise the same
+ * as when it is integrated alone.                                                             */
+int ridc_integrate_batch(ridc_handle* const* hs, int32_t count, const double* const* u0,
+                         const int64_t* nsteps, double* const* uT);
+
+/* ---- stepping interface (continuous batching) ---------------------------------------------- */
+/* Load u0 into every level and arm the handle for nsteps time steps (pipeline step 0).       */
+int ridc_begin(ridc_handle* h, const double* u0_dev, int64_t nsteps);
+
+/* Advance each armed handle by min(max_steps, its remaining) pipeline steps.  Handles that
+ * share a pipeline step are grouped into shared launches.  All handles must share a stream.  */
+int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps);
+
+/* Pipeline steps left before ridc_read may be called (0 when done; -1 if never armed).        */
+int64_t ridc_remaining(const ridc_handle* h);
+
+/* Copy the top level (uT_dev) and optionally every level (levels_dev, nullable, level-major)
+ * out of a handle whose remaining() is 0.  Errors: RIDC_E_STATE if steps remain.              */
+int ridc_read(ridc_handle* h, double* uT_dev, double* levels_dev);
+
+/* Wait for the handle's stream; RIDC_E_NONFINITE if the last result read held a NaN/Inf.     */
+int ridc_sync(ridc_handle* h);
+
+/* Thread-local message for the last failing call on this thread ("" if none).                 */
+const char* ridc_last_error(void);
+
+/* ---- introspection (host only, no device work) --------------------------------------------- */
+/* Quadrature weights of corrector j for start-up row r (0 <= r < j): the j+1 integrals, in
+ * units of dt, of the Lagrange basis on nodes t_s..t_{s+j} over [t_{s+r}, t_{s+r+1}]
+ * (section III-C; row r = j-1 is the steady-state trailing window).  out: j+1 doubles,
+ * ascending node order.                                                                       */
+int ridc_quadrature_weights(int32_t j, int32_t r, double* out);
+
+/* Number of PCR stages and the final divisor the 1D solver uses for (I - r*D2) on a cycle of
+ * length m (periodic: m = n; Dirichlet: m = 2n+2, odd extension), r = dt*nu/h^2.             */
+int ridc_pcr_plan(double r, int64_t m, int32_t* stages, double* divisor);
+
+/* Kernel names and per-launch algorithmic work of the handle's dominant kernel: bytes moved
+ * per pipeline step at steady state (1D) or flops per step of the 2D transforms.             */
+int ridc_step_cost(const ridc_handle* h, double* hbm_bytes, double* flops);
+
+/* Library version string.                                                                     */
+const char* ridc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIDC_H */

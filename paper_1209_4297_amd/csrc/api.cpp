@@ -1,0 +1,709 @@
+// C ABI of the RIDC library: handle lifetime, pipeline scheduling and batching (host side).
+//
+// Pipeline schedule (section III, Fig. 1 and Fig. 2; section III-E): at pipeline step s level j
+// computes time index m = s - j(j+1)/2.  Level j computing t_{n+1} reads level j-1 at
+// t_{max(0,n+1-j)} .. t_{max(n+1,j)}, all produced at step s-1 or earlier, so every active level
+// of a step is independent and one launch (1D) or one group of launches (2D) covers them all.
+// The integration takes nt + P(P-1)/2 steps, the last P(P-1)/2 being the drain of section
+// III-E.  Level j < P-1 keeps its last 2j+3 values in a ring (the window level j+1 still reads
+// plus the slot being written); the top level ping-pongs between 2 slots.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "ridc2d.h"
+#include "ridc_internal.h"
+
+namespace ridc {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+}  // namespace ridc
+
+using namespace ridc;
+
+struct ridc_handle {
+  ridc_problem p{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int P = 1;
+  int64_t npts = 0;  // unknowns (n or n*n)
+  double h = 0.0;
+
+  char* pool = nullptr;  // one device allocation holding everything below
+  size_t pool_bytes = 0;
+  std::vector<double*> ring;  // ring base per level
+  std::vector<int> R;         // ring slots per level
+  double* W = nullptr;        // weights; level j at W + woff[j] (j rows x (j+1), ascending nodes)
+  std::vector<int64_t> woff;
+  int* flag = nullptr;        // non-finite flag
+
+  // state of the current integration
+  int64_t nt = -1;
+  int64_t sigma = 0;
+  int64_t total = 0;
+
+  // 1D plan
+  PcrPlan pcr;
+  int threads = 256;
+  std::vector<Lvl1D> proto;   // one item per level (sigma0 = 0, nt of the armed integration)
+  std::vector<Blk1D> blocks;  // blocks of a solo launch
+  Lvl1D* d_items = nullptr;   // device copies (inside the pool)
+  Blk1D* d_blocks = nullptr;
+  size_t lds = 0;
+
+  // 2D plan
+  Plan2D* p2 = nullptr;
+
+  // graph of a whole integration, cached per nt
+  hipGraphExec_t gexec = nullptr;
+  int64_t graph_nt = -1;
+};
+
+namespace {
+
+bool env_flag(const char* name, bool dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return !(v[0] == '0' || v[0] == 'n' || v[0] == 'N' || v[0] == 'f' || v[0] == 'F');
+}
+
+int validate(const ridc_problem* p) {
+  if (!p) return fail(RIDC_E_INVAL, "problem is NULL");
+  if (p->dim != 1 && p->dim != 2) return fail(RIDC_E_INVAL, "dim must be 1 or 2");
+  if (p->bc != RIDC_BC_PERIODIC && p->bc != RIDC_BC_DIRICHLET0)
+    return fail(RIDC_E_INVAL, "unknown boundary condition");
+  if (p->n < 2) return fail(RIDC_E_INVAL, "n must be >= 2");
+  if (!(p->length > 0.0) || !std::isfinite(p->length))
+    return fail(RIDC_E_INVAL, "length must be > 0");
+  if (p->order < 1 || p->order > RIDC_MAX_ORDER)
+    return fail(RIDC_E_INVAL, "order must be in 1..12");
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(RIDC_E_INVAL, "dt must be > 0");
+  if (!(p->nu >= 0.0) || !std::isfinite(p->nu)) return fail(RIDC_E_INVAL, "nu must be >= 0");
+  if (!std::isfinite(p->a)) return fail(RIDC_E_INVAL, "a must be finite");
+  if (p->fe_kind < RIDC_FE_NONE || p->fe_kind > RIDC_FE_LOGISTIC)
+    return fail(RIDC_E_INVAL, "unknown explicit term");
+  if (p->prec < RIDC_PREC_FP64 || p->prec > RIDC_PREC_BF16X3_REFINE)
+    return fail(RIDC_E_INVAL, "unknown precision");
+  if (p->reserved != 0) return fail(RIDC_E_INVAL, "reserved must be 0");
+  if (p->dim == 2) {
+    if (p->bc != RIDC_BC_DIRICHLET0)
+      return fail(RIDC_E_UNSUPPORTED, "2D supports Dirichlet boundaries only");
+    if (p->fe_kind == RIDC_FE_ADVECT_C2)
+      return fail(RIDC_E_UNSUPPORTED, "2D advection is not provided");
+    return plan2d_validate(p);
+  }
+  if (p->prec != RIDC_PREC_FP64) return fail(RIDC_E_UNSUPPORTED, "1D computes in FP64 only");
+  if (p->n > (1 << 28)) return fail(RIDC_E_UNSUPPORTED, "1D n above 2^28");
+  return RIDC_OK;
+}
+
+double grid_h(const ridc_problem* p) {
+  return p->bc == RIDC_BC_PERIODIC ? p->length / (double)p->n : p->length / (double)(p->n + 1);
+}
+
+int device_max_lds() {
+  static int cached = -1;
+  if (cached < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v > 0)
+      cached = v;
+    else
+      cached = 65536;
+  }
+  return cached;
+}
+
+// ---------------------------------------------------------------------------------------------
+// 1D tiling (result-neutral: every tiling performs the same operations for every output row)
+// ---------------------------------------------------------------------------------------------
+struct Tile1D {
+  int wrap = 1;
+  int B = 0;
+  int threads = 256;
+};
+
+std::mutex g_tune_mu;
+struct TuneKey {
+  int64_t n;
+  int bc;
+  int stages;
+};
+std::vector<std::pair<TuneKey, Tile1D>> g_tuned;
+
+bool tuned_tile(int64_t n, int bc, int stages, Tile1D* t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : g_tuned)
+    if (e.first.n == n && e.first.bc == bc && e.first.stages == stages) {
+      *t = e.second;
+      return true;
+    }
+  return false;
+}
+
+int64_t halo_rows(const PcrPlan& pcr) {
+  return pcr.stages < 30 ? ((int64_t)1 << pcr.stages) - 1 : ((int64_t)1 << 40);
+}
+
+bool tile_fits(const ridc_problem* p, const PcrPlan& pcr, const Tile1D& t) {
+  const int64_t M = p->bc == RIDC_BC_PERIODIC ? p->n : 2 * p->n + 2;
+  const int64_t ms = p->bc == RIDC_BC_PERIODIC ? p->n : p->n + 2;
+  if (t.threads != 64 && t.threads != 128 && t.threads != 256 && t.threads != 512 &&
+      t.threads != 1024)
+    return false;
+  if (t.wrap) return 2 * sizeof(double) * (size_t)ms <= (size_t)device_max_lds();
+  const int64_t H = halo_rows(pcr);
+  if (pcr.exact || H >= M || t.B < 1) return false;
+  return 2 * sizeof(double) * (size_t)(t.B + 2 * H) <= (size_t)device_max_lds();
+}
+
+int choose_tile_1d(const ridc_problem* p, const PcrPlan& pcr, Tile1D* out) {
+  Tile1D t;
+  if (tuned_tile(p->n, p->bc, pcr.stages, &t) && tile_fits(p, pcr, t)) {
+    *out = t;
+    return RIDC_OK;
+  }
+  const int64_t H = halo_rows(pcr);
+  // default: chunks of 1024 rows when the system is long and the halo is small against them
+  Tile1D chunk{0, 1024, 256};
+  if (p->n >= 2048 && H <= 512 && tile_fits(p, pcr, chunk)) {
+    *out = chunk;
+    return RIDC_OK;
+  }
+  Tile1D wrap{1, 0, 256};
+  if (tile_fits(p, pcr, wrap)) {
+    *out = wrap;
+    return RIDC_OK;
+  }
+  if (tile_fits(p, pcr, chunk)) {
+    *out = chunk;
+    return RIDC_OK;
+  }
+  return fail(RIDC_E_UNSUPPORTED, "1D system does not fit one workgroup's LDS");
+}
+
+int plan_1d(const ridc_problem* p, PcrPlan* pcr, Tile1D* tile) {
+  const double h = grid_h(p);
+  const double r = p->dt * p->nu / (h * h);
+  const int64_t M = p->bc == RIDC_BC_PERIODIC ? p->n : 2 * p->n + 2;
+  if (!pcr_plan(r, M, pcr))
+    return fail(RIDC_E_UNSUPPORTED, "PCR did not converge within the stage cap");
+  return choose_tile_1d(p, *pcr, tile);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t rings = 0, weights = 0, flag = 0, items = 0, blocks = 0, ws2d = 0, total = 0;
+  int64_t nblocks = 0;
+};
+
+void plan_layout(const ridc_problem* p, const Tile1D* tile, Layout* L) {
+  const int P = p->order;
+  const int64_t npts = p->dim == 1 ? p->n : p->n * p->n;
+  int64_t slots = 0;
+  for (int j = 0; j < P; ++j) slots += ring_slots(j, P);
+  L->rings = align256(sizeof(double) * (size_t)(slots * npts));
+  int64_t nw = 0;
+  for (int j = 1; j < P; ++j) nw += (int64_t)j * (j + 1);
+  L->weights = align256(sizeof(double) * (size_t)std::max<int64_t>(nw, 1));
+  L->flag = 256;
+  if (p->dim == 1) {
+    const int64_t nchunks = tile->wrap ? 1 : (p->n + tile->B - 1) / tile->B;
+    L->nblocks = nchunks * P;
+    L->items = align256(sizeof(Lvl1D) * P);
+    L->blocks = align256(sizeof(Blk1D) * (size_t)L->nblocks);
+  } else {
+    L->ws2d = align256(plan2d_workspace_bytes(p));
+  }
+  L->total = L->rings + L->weights + L->flag + L->items + L->blocks + L->ws2d;
+}
+
+void build_items_1d(ridc_handle* h, const Tile1D& tile) {
+  const ridc_problem& p = h->p;
+  const int P = h->P;
+  h->proto.assign(P, Lvl1D{});
+  const int64_t M = p.bc == RIDC_BC_PERIODIC ? p.n : 2 * p.n + 2;
+  const int H = tile.wrap ? 0 : (int)halo_rows(h->pcr);
+  const int nchunks = tile.wrap ? 1 : (int)((p.n + tile.B - 1) / tile.B);
+  for (int j = 0; j < P; ++j) {
+    Lvl1D& it = h->proto[j];
+    it.own = h->ring[j];
+    it.prev = j > 0 ? h->ring[j - 1] : nullptr;
+    it.W = j > 0 ? h->W + h->woff[j] : nullptr;
+    it.nt = 0;
+    it.sigma0 = 0;
+    it.n = (int32_t)p.n;
+    it.j = j;
+    it.R_own = h->R[j];
+    it.R_prev = j > 0 ? h->R[j - 1] : 1;
+    it.bc = p.bc;
+    it.fe = p.fe_kind;
+    it.stages = h->pcr.stages;
+    it.wrap = tile.wrap;
+    it.M = (int32_t)M;
+    it.B = tile.wrap ? 0 : tile.B;
+    it.H = H;
+    it.nchunks = nchunks;
+    it.dt = p.dt;
+    it.a_2h = p.a / (2.0 * h->h);
+    it.nu_h2 = p.nu / (h->h * h->h);
+    it.divisor = h->pcr.divisor;
+    for (int k = 0; k < h->pcr.stages; ++k) {
+      it.gamma[k] = h->pcr.gamma[k];
+      it.shift[k] = (int32_t)h->pcr.shift[k];
+    }
+  }
+  h->blocks.clear();
+  for (int j = 0; j < P; ++j)
+    for (int c = 0; c < nchunks; ++c) h->blocks.push_back(Blk1D{j, c});
+  size_t lds = 0;
+  for (auto& it : h->proto) lds = std::max(lds, lds_bytes_1d(it));
+  h->lds = lds;
+  h->threads = tile.threads;
+}
+
+// Grouped launch tables for ridc_advance over several 1D handles (one set per thread and
+// device; uploads are ordered on the stream, the pinned staging copy is reused only after the
+// previous upload completed).
+struct BatchArena {
+  int device = -1;
+  Lvl1D* d_items = nullptr;
+  Blk1D* d_blocks = nullptr;
+  size_t cap_items = 0, cap_blocks = 0;
+  Lvl1D* h_items = nullptr;
+  Blk1D* h_blocks = nullptr;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+
+thread_local BatchArena g_arena;
+
+int arena_reserve(size_t nitems, size_t nblocks) {
+  int dev = 0;
+  RIDC_HIP_TRY(hipGetDevice(&dev));
+  if (g_arena.device != dev) {
+    g_arena = BatchArena{};  // tables of another device are left to process teardown
+    g_arena.device = dev;
+  }
+  if (!g_arena.done) RIDC_HIP_TRY(hipEventCreateWithFlags(&g_arena.done, hipEventDisableTiming));
+  if (g_arena.pending) {
+    RIDC_HIP_TRY(hipEventSynchronize(g_arena.done));
+    g_arena.pending = false;
+  }
+  if (nitems > g_arena.cap_items) {
+    if (g_arena.d_items) (void)hipFree(g_arena.d_items);
+    if (g_arena.h_items) (void)hipHostFree(g_arena.h_items);
+    g_arena.d_items = nullptr;
+    g_arena.h_items = nullptr;
+    const size_t cap = std::max<size_t>(nitems, 2 * g_arena.cap_items);
+    if (hipMalloc(&g_arena.d_items, cap * sizeof(Lvl1D)) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "batch item table");
+    if (hipHostMalloc(&g_arena.h_items, cap * sizeof(Lvl1D), hipHostMallocDefault) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "batch item staging");
+    g_arena.cap_items = cap;
+  }
+  if (nblocks > g_arena.cap_blocks) {
+    if (g_arena.d_blocks) (void)hipFree(g_arena.d_blocks);
+    if (g_arena.h_blocks) (void)hipHostFree(g_arena.h_blocks);
+    g_arena.d_blocks = nullptr;
+    g_arena.h_blocks = nullptr;
+    const size_t cap = std::max<size_t>(nblocks, 2 * g_arena.cap_blocks);
+    if (hipMalloc(&g_arena.d_blocks, cap * sizeof(Blk1D)) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "batch block table");
+    if (hipHostMalloc(&g_arena.h_blocks, cap * sizeof(Blk1D), hipHostMallocDefault) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "batch block staging");
+    g_arena.cap_blocks = cap;
+  }
+  return RIDC_OK;
+}
+
+int64_t pipeline_steps(int64_t nt, int P) { return nt > 0 ? nt + (int64_t)P * (P - 1) / 2 : 0; }
+
+int upload_solo_items(ridc_handle* h) {
+  for (auto& it : h->proto) it.nt = h->nt;
+  RIDC_HIP_TRY(hipMemcpyAsync(h->d_items, h->proto.data(), sizeof(Lvl1D) * h->proto.size(),
+                              hipMemcpyHostToDevice, h->stream));
+  return RIDC_OK;
+}
+
+int launch_solo_steps_1d(ridc_handle* h, int64_t first, int64_t last) {
+  for (int64_t s = first; s <= last; ++s)
+    RIDC_HIP_TRY(launch_1d_step(h->d_items, h->d_blocks, (int)h->blocks.size(), h->threads,
+                                h->lds, s, h->stream));
+  return RIDC_OK;
+}
+
+int run_solo_steps(ridc_handle* h, int64_t first, int64_t last) {
+  if (h->p.dim == 1) return launch_solo_steps_1d(h, first, last);
+  Plan2D* pl = h->p2;
+  for (int64_t s = first; s <= last; ++s) {
+    int rc = plan2d_step(&pl, 1, &s, h->stream);
+    if (rc != RIDC_OK) return rc;
+  }
+  return RIDC_OK;
+}
+
+int check_handles(ridc_handle* const* hs, int32_t count) {
+  if (count < 0 || (count > 0 && !hs)) return fail(RIDC_E_INVAL, "bad handle list");
+  for (int32_t i = 0; i < count; ++i) {
+    if (!hs[i]) return fail(RIDC_E_INVAL, "NULL handle in list");
+    if (hs[i]->stream != hs[0]->stream)
+      return fail(RIDC_E_INVAL, "batched handles must share one stream");
+  }
+  return RIDC_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+const char* ridc_version(void) { return "ridc-gfx950 0.1"; }
+
+const char* ridc_last_error(void) { return ridc::g_last_error.c_str(); }
+
+int ridc_quadrature_weights(int32_t j, int32_t r, double* out) {
+  if (!out) return fail(RIDC_E_INVAL, "out is NULL");
+  if (!quadrature_weights(j, r, out)) return fail(RIDC_E_INVAL, "need 1 <= j < 12, 0 <= r < j");
+  return RIDC_OK;
+}
+
+int ridc_pcr_plan(double r, int64_t m, int32_t* stages, double* divisor) {
+  PcrPlan pl;
+  if (!pcr_plan(r, m, &pl)) return fail(RIDC_E_INVAL, "bad PCR parameters");
+  if (stages) *stages = pl.stages;
+  if (divisor) *divisor = pl.divisor;
+  return RIDC_OK;
+}
+
+size_t ridc_footprint_bytes(const ridc_problem* p) {
+  if (validate(p) != RIDC_OK) return 0;
+  Layout L;
+  if (p->dim == 1) {
+    PcrPlan pcr;
+    Tile1D tile;
+    if (plan_1d(p, &pcr, &tile) != RIDC_OK) return 0;
+    plan_layout(p, &tile, &L);
+  } else {
+    plan_layout(p, nullptr, &L);
+  }
+  return L.total;
+}
+
+int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out) {
+  if (!out) return fail(RIDC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc != RIDC_OK) return rc;
+  auto* h = new ridc_handle();
+  h->p = *p;
+  h->stream = (hipStream_t)hip_stream;
+  h->P = p->order;
+  h->npts = p->dim == 1 ? p->n : p->n * p->n;
+  h->h = grid_h(p);
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(RIDC_E_HIP, "hipGetDevice failed");
+  }
+  Tile1D tile;
+  if (p->dim == 1) {
+    rc = plan_1d(p, &h->pcr, &tile);
+    if (rc != RIDC_OK) {
+      delete h;
+      return rc;
+    }
+  }
+  Layout L;
+  plan_layout(p, &tile, &L);
+  if (hipMalloc(&h->pool, L.total) != hipSuccess) {
+    (void)hipGetLastError();
+    delete h;
+    return fail(RIDC_E_NOMEM, "device allocation of " + std::to_string(L.total) + " bytes failed");
+  }
+  h->pool_bytes = L.total;
+  char* cur = h->pool;
+  double* rings = (double*)cur;
+  cur += L.rings;
+  h->W = (double*)cur;
+  cur += L.weights;
+  h->flag = (int*)cur;
+  cur += L.flag;
+  h->ring.resize(h->P);
+  h->R.resize(h->P);
+  double* rp = rings;
+  for (int j = 0; j < h->P; ++j) {
+    h->R[j] = ring_slots(j, h->P);
+    h->ring[j] = rp;
+    rp += (int64_t)h->R[j] * h->npts;
+  }
+  // weights: level j, rows r = 0..j-1, ascending nodes
+  std::vector<double> w;
+  h->woff.assign(h->P, 0);
+  for (int j = 1; j < h->P; ++j) {
+    h->woff[j] = (int64_t)w.size();
+    for (int r = 0; r < j; ++r) {
+      double row[kMaxOrder + 1];
+      quadrature_weights(j, r, row);
+      w.insert(w.end(), row, row + j + 1);
+    }
+  }
+  if (!w.empty() &&
+      hipMemcpy(h->W, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    ridc_destroy(h);
+    return fail(RIDC_E_HIP, "weight upload failed");
+  }
+  if (hipMemset(h->flag, 0, sizeof(int)) != hipSuccess) {
+    ridc_destroy(h);
+    return fail(RIDC_E_HIP, "flag init failed");
+  }
+  if (p->dim == 1) {
+    h->d_items = (Lvl1D*)cur;
+    cur += L.items;
+    h->d_blocks = (Blk1D*)cur;
+    cur += L.blocks;
+    build_items_1d(h, tile);
+    if (hipMemcpy(h->d_blocks, h->blocks.data(), sizeof(Blk1D) * h->blocks.size(),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      ridc_destroy(h);
+      return fail(RIDC_E_HIP, "block table upload failed");
+    }
+  } else {
+    rc = plan2d_create(p, h->h, h->ring.data(), h->R.data(), h->W, h->woff.data(), cur, L.ws2d,
+                       h->stream, &h->p2);
+    if (rc != RIDC_OK) {
+      ridc_destroy(h);
+      return rc;
+    }
+  }
+  *out = h;
+  return RIDC_OK;
+}
+
+int ridc_destroy(ridc_handle* h) {
+  if (!h) return RIDC_OK;
+  (void)hipStreamSynchronize(h->stream);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->p2) plan2d_destroy(h->p2);
+  if (h->pool) (void)hipFree(h->pool);
+  delete h;
+  return RIDC_OK;
+}
+
+int ridc_begin(ridc_handle* h, const double* u0_dev, int64_t nsteps) {
+  if (!h || !u0_dev) return fail(RIDC_E_INVAL, "NULL handle or u0");
+  if (nsteps < 0) return fail(RIDC_E_INVAL, "nsteps must be >= 0");
+  if (nsteps > 0 && nsteps < h->P - 1)
+    return fail(RIDC_E_INVAL, "nsteps must be 0 or >= order-1 (start-up quadrature)");
+  // every level starts from the initial data (section III-E, Fig. 2): slot 0 of each ring
+  for (int j = 0; j < h->P; ++j)
+    RIDC_HIP_TRY(hipMemcpyAsync(h->ring[j], u0_dev, sizeof(double) * h->npts,
+                                hipMemcpyDeviceToDevice, h->stream));
+  h->nt = nsteps;
+  h->sigma = 0;
+  h->total = pipeline_steps(nsteps, h->P);
+  if (h->p.dim == 1) return upload_solo_items(h);
+  return plan2d_arm(h->p2, nsteps, h->stream);
+}
+
+int64_t ridc_remaining(const ridc_handle* h) {
+  if (!h || h->nt < 0) return -1;
+  return h->total - h->sigma;
+}
+
+int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
+  int rc = check_handles(hs, count);
+  if (rc != RIDC_OK) return rc;
+  if (max_steps < 0) return fail(RIDC_E_INVAL, "max_steps must be >= 0");
+  for (int32_t i = 0; i < count; ++i)
+    if (hs[i]->nt < 0) return fail(RIDC_E_STATE, "handle not armed (call ridc_begin)");
+  if (count == 0 || max_steps == 0) return RIDC_OK;
+  hipStream_t stream = hs[0]->stream;
+  int64_t steps = 0;
+  for (int32_t i = 0; i < count; ++i)
+    steps = std::max(steps, std::min(max_steps, hs[i]->total - hs[i]->sigma));
+  if (steps == 0) return RIDC_OK;
+  if (count == 1) {
+    ridc_handle* h = hs[0];
+    const int64_t k = std::min(max_steps, h->total - h->sigma);
+    rc = run_solo_steps(h, h->sigma + 1, h->sigma + k);
+    if (rc != RIDC_OK) return rc;
+    h->sigma += k;
+    return RIDC_OK;
+  }
+  // ---- 1D handles: one grouped launch per pipeline step --------------------------------------
+  std::vector<ridc_handle*> h1, h2;
+  for (int32_t i = 0; i < count; ++i) {
+    if (hs[i]->total - hs[i]->sigma <= 0) continue;
+    (hs[i]->p.dim == 1 ? h1 : h2).push_back(hs[i]);
+  }
+  if (!h1.empty()) {
+    size_t nitems = 0, nblocks = 0;
+    for (auto* h : h1) {
+      nitems += h->proto.size();
+      nblocks += h->blocks.size();
+    }
+    rc = arena_reserve(nitems, nblocks);
+    if (rc != RIDC_OK) return rc;
+    size_t ii = 0, bi = 0, lds = 0;
+    int threads = 0;
+    for (auto* h : h1) {
+      for (size_t j = 0; j < h->proto.size(); ++j) {
+        Lvl1D it = h->proto[j];
+        it.nt = h->nt;
+        it.sigma0 = -h->sigma;  // the handle's own step = launch step + sigma
+        g_arena.h_items[ii + j] = it;
+      }
+      for (auto b : h->blocks) g_arena.h_blocks[bi++] = Blk1D{(int32_t)(ii + b.item), b.chunk};
+      ii += h->proto.size();
+      lds = std::max(lds, h->lds);
+      threads = std::max(threads, h->threads);
+    }
+    RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_items, g_arena.h_items, sizeof(Lvl1D) * nitems,
+                                hipMemcpyHostToDevice, stream));
+    RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_blocks, g_arena.h_blocks, sizeof(Blk1D) * nblocks,
+                                hipMemcpyHostToDevice, stream));
+    RIDC_HIP_TRY(hipEventRecord(g_arena.done, stream));
+    g_arena.pending = true;
+    int64_t steps1 = 0;
+    for (auto* h : h1) steps1 = std::max(steps1, std::min(max_steps, h->total - h->sigma));
+    for (int64_t s = 1; s <= steps1; ++s)
+      RIDC_HIP_TRY(launch_1d_step(g_arena.d_items, g_arena.d_blocks, (int)nblocks, threads, lds,
+                                  s, stream));
+    for (auto* h : h1) h->sigma += std::min(max_steps, h->total - h->sigma);
+  }
+  // ---- 2D handles: grouped per step by the 2D planner -----------------------------------------
+  if (!h2.empty()) {
+    std::vector<Plan2D*> plans;
+    std::vector<int64_t> sig;
+    int64_t steps2 = 0;
+    for (auto* h : h2) {
+      plans.push_back(h->p2);
+      steps2 = std::max(steps2, std::min(max_steps, h->total - h->sigma));
+    }
+    for (int64_t s = 1; s <= steps2; ++s) {
+      sig.clear();
+      for (auto* h : h2) sig.push_back(h->sigma + s);
+      rc = plan2d_step(plans.data(), (int)plans.size(), sig.data(), stream);
+      if (rc != RIDC_OK) return rc;
+    }
+    for (auto* h : h2) h->sigma += std::min(max_steps, h->total - h->sigma);
+  }
+  return RIDC_OK;
+}
+
+int ridc_read(ridc_handle* h, double* uT_dev, double* levels_dev) {
+  if (!h) return fail(RIDC_E_INVAL, "NULL handle");
+  if (h->nt < 0) return fail(RIDC_E_STATE, "handle not armed");
+  if (h->sigma != h->total) return fail(RIDC_E_STATE, "pipeline steps remain");
+  const size_t bytes = sizeof(double) * h->npts;
+  const int top = h->P - 1;
+  const double* src = h->ring[top] + (h->nt % h->R[top]) * h->npts;
+  if (uT_dev) {
+    RIDC_HIP_TRY(hipMemcpyAsync(uT_dev, src, bytes, hipMemcpyDeviceToDevice, h->stream));
+    RIDC_HIP_TRY(launch_nonfinite_check(uT_dev, h->npts, h->flag, h->stream));
+  }
+  if (levels_dev) {
+    for (int j = 0; j < h->P; ++j)
+      RIDC_HIP_TRY(hipMemcpyAsync(levels_dev + (int64_t)j * h->npts,
+                                  h->ring[j] + (h->nt % h->R[j]) * h->npts, bytes,
+                                  hipMemcpyDeviceToDevice, h->stream));
+  }
+  return RIDC_OK;
+}
+
+int ridc_sync(ridc_handle* h) {
+  if (!h) return fail(RIDC_E_INVAL, "NULL handle");
+  RIDC_HIP_TRY(hipStreamSynchronize(h->stream));
+  int f = 0;
+  RIDC_HIP_TRY(hipMemcpy(&f, h->flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (f) {
+    RIDC_HIP_TRY(hipMemset(h->flag, 0, sizeof(int)));
+    return fail(RIDC_E_NONFINITE, "result holds a NaN or Inf");
+  }
+  return RIDC_OK;
+}
+
+int ridc_integrate(ridc_handle* h, const double* u0_dev, int64_t nsteps, double* uT_dev,
+                   double* levels_dev) {
+  int rc = ridc_begin(h, u0_dev, nsteps);
+  if (rc != RIDC_OK) return rc;
+  const bool use_graph = h->stream != nullptr && h->total > 0 && env_flag("RIDC_GRAPH", true);
+  if (use_graph) {
+    if (h->graph_nt != nsteps) {
+      if (h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+      }
+      h->graph_nt = -1;
+      hipGraph_t g = nullptr;
+      RIDC_HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      rc = run_solo_steps(h, 1, h->total);
+      hipError_t e = hipStreamEndCapture(h->stream, &g);
+      if (rc != RIDC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(RIDC_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(RIDC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+      h->graph_nt = nsteps;
+    }
+    RIDC_HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+    h->sigma = h->total;
+  } else {
+    rc = ridc_advance(&h, 1, h->total);
+    if (rc != RIDC_OK) return rc;
+  }
+  return ridc_read(h, uT_dev, levels_dev);
+}
+
+int ridc_integrate_batch(ridc_handle* const* hs, int32_t count, const double* const* u0,
+                         const int64_t* nsteps, double* const* uT) {
+  int rc = check_handles(hs, count);
+  if (rc != RIDC_OK) return rc;
+  if (count > 0 && (!u0 || !nsteps || !uT)) return fail(RIDC_E_INVAL, "NULL array argument");
+  int64_t most = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    rc = ridc_begin(hs[i], u0[i], nsteps[i]);
+    if (rc != RIDC_OK) return rc;
+    most = std::max(most, hs[i]->total);
+  }
+  rc = ridc_advance(hs, count, most);
+  if (rc != RIDC_OK) return rc;
+  for (int32_t i = 0; i < count; ++i) {
+    rc = ridc_read(hs[i], uT[i], nullptr);
+    if (rc != RIDC_OK) return rc;
+  }
+  return RIDC_OK;
+}
+
+int ridc_step_cost(const ridc_handle* h, double* hbm_bytes, double* flops) {
+  if (!h) return fail(RIDC_E_INVAL, "NULL handle");
+  // steady state, all levels active: level 0 reads its value and writes one; level j >= 1 reads
+  // its value and the j+1 window values of level j-1 and writes one
+  double vectors = 0;
+  for (int j = 0; j < h->P; ++j) vectors += j == 0 ? 2 : j + 3;
+  double b = vectors * sizeof(double) * (double)h->npts;
+  double f = 0;
+  if (h->p.dim == 2) plan2d_cost(h->p2, &b, &f);
+  if (hbm_bytes) *hbm_bytes = b;
+  if (flops) *flops = f;
+  return RIDC_OK;
+}
+
+}  // extern "C"

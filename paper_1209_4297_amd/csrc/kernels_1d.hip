@@ -1,0 +1,256 @@
+// 1D level-step kernel of the RIDC pipeline for gfx950.
+//
+// One launch advances every active (instance, level) work item of a batch by one pipeline step.
+// A workgroup owns one work item, or one chunk of it, and fuses:
+//   1. the right-hand side of the level's IMEX Euler step, computed straight from the level
+//      rings: the predictor (section II, eq. imex_diffusion) or the corrector (section III-C,
+//      eq. corr) with the (j+1)-node quadrature of f = f_E + f_I along level j-1;
+//   2. the implicit solve (I - dt nu D2) x = rhs by parallel cyclic reduction in LDS;
+//   3. the store of the new level value into the level's ring.
+// Nothing but the new level value is written to HBM; f along the previous level is recomputed
+// from that level's stored values (a 3-point stencil), so a step reads j+2 vectors for
+// level j and writes one.
+//
+// Solve.  The matrix is tridiagonal with constant coefficients b = 1 + 2r, a = -r
+// (r = dt nu / h^2).  Periodic grids give a cyclic system on m = n rows.  Dirichlet grids
+// (zero ghosts) are solved as the odd extension to a cyclic system of m = 2n+2 rows (row 0 and
+// row n+1 are the ghosts, rows n+2.. mirror rows n..1 with a sign flip), which reproduces the
+// Dirichlet solution exactly.  Each PCR stage k updates every row with the same coefficient:
+// d_i <- d_i - gamma_k (d_{i-s} + d_{i+s}), s = 2^k mod m; after the last stage x = d / divisor.
+// In "wrap" mode one workgroup holds the whole cycle and indexes it modulo m.  In "chunk" mode
+// (used when the coupling falls below rounding after K stages) a workgroup computes B rows
+// and carries a halo of 2^K - 1 rows on each side, recomputing the halo's right-hand side; the
+// valid region shrinks by 2^k per stage.  Both modes perform the same operations on the same
+// values for every output row, so results do not depend on the tiling.
+#include "ridc_internal.h"
+
+namespace ridc {
+
+namespace {
+
+__device__ __forceinline__ double fe_eval(int fe, double a_2h, double um, double u0, double up) {
+  if (fe == RIDC_FE_ADVECT_C2) return -a_2h * (up - um);
+  if (fe == RIDC_FE_LOGISTIC) return u0 * (1.0 - u0);
+  return 0.0;
+}
+
+// v at physical row p (-1 <= p <= n) under the grid's boundary rule
+__device__ __forceinline__ double at(const double* __restrict__ v, int p, int n, bool periodic) {
+  if (p < 0) return periodic ? v[p + n] : 0.0;
+  if (p >= n) return periodic ? v[p - n] : 0.0;
+  return v[p];
+}
+
+struct Ctx {
+  const double* u;     // eta[j]_n
+  double* out;         // slot of eta[j]_{n+1}
+  const double* w;     // weights row (j >= 1)
+  int64_t nidx;        // n
+  int64_t s;           // first window node
+};
+
+// Right-hand side of the level-j step at physical row p.
+__device__ __forceinline__ double rhs_at(const Lvl1D& L, const Ctx& c, int p) {
+  const int n = L.n;
+  const bool per = L.bc == RIDC_BC_PERIODIC;
+  const double um = at(c.u, p - 1, n, per);
+  const double u0 = c.u[p];
+  const double up = at(c.u, p + 1, n, per);
+  const double fe_u = fe_eval(L.fe, L.a_2h, um, u0, up);
+  if (L.j == 0) return u0 + L.dt * fe_u;
+  double quad = 0.0, fe_n = 0.0, li_n1 = 0.0;
+  for (int i = 0; i <= L.j; ++i) {
+    const int64_t node = c.s + i;
+    const double* v = L.prev + (node % L.R_prev) * (int64_t)n;
+    const double vm = at(v, p - 1, n, per);
+    const double v0 = v[p];
+    const double vp = at(v, p + 1, n, per);
+    const double li = L.nu_h2 * ((vm + vp) - 2.0 * v0);
+    const double fe = fe_eval(L.fe, L.a_2h, vm, v0, vp);
+    quad += c.w[i] * (fe + li);
+    if (node == c.nidx) fe_n = fe;
+    if (node == c.nidx + 1) li_n1 = li;
+  }
+  return u0 + L.dt * fe_u - L.dt * (li_n1 + fe_n) + L.dt * quad;
+}
+
+// Right-hand side of row g of the odd/periodic extension (g in [0, M)).
+__device__ __forceinline__ double rhs_ext(const Lvl1D& L, const Ctx& c, int g) {
+  if (L.bc == RIDC_BC_PERIODIC) return rhs_at(L, c, g);
+  const int n = L.n;
+  if (g == 0 || g == n + 1) return 0.0;
+  if (g <= n) return rhs_at(L, c, g - 1);
+  return -rhs_at(L, c, L.M - g - 1);
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
+                                              const Blk1D* __restrict__ blocks, int64_t sigma) {
+  extern __shared__ double lds[];
+  const Blk1D bk = blocks[blockIdx.x];
+  const Lvl1D& L = items[bk.item];
+  const int j = L.j;
+  const int64_t m = sigma - L.sigma0 - (int64_t)j * (j + 1) / 2;   // time index computed now
+  if (m < 1 || m > L.nt) return;                                    // level idle this step
+  const int n = L.n;
+  Ctx c;
+  c.nidx = m - 1;
+  c.u = L.own + (c.nidx % L.R_own) * (int64_t)n;
+  c.out = L.own + (m % L.R_own) * (int64_t)n;
+  c.s = 0;
+  c.w = nullptr;
+  if (j > 0) {
+    c.s = m - j > 0 ? m - j : 0;                      // window t_s..t_{s+j}
+    c.w = L.W + (c.nidx - c.s) * (j + 1);             // row r = n - s
+  }
+  const bool per = L.bc == RIDC_BC_PERIODIC;
+  const int M = L.M;
+
+  if (L.wrap) {
+    const int ms = per ? n : n + 2;                   // stored rows of the cycle
+    double* d0 = lds;
+    double* d1 = lds + ms;
+    for (int l = threadIdx.x; l < ms; l += T) {
+      d0[l] = rhs_ext(L, c, l);
+      d1[l] = 0.0;
+    }
+    __syncthreads();
+    const int l0 = per ? 0 : 1, l1 = per ? n : n + 1;  // Dirichlet ghosts stay zero
+    for (int k = 0; k < L.stages; ++k) {
+      const int sh = L.shift[k];
+      const double g = L.gamma[k];
+      for (int l = l0 + threadIdx.x; l < l1; l += T) {
+        int ia = l - sh;
+        if (ia < 0) ia += M;
+        int ib = l + sh;
+        if (ib >= M) ib -= M;
+        double da, db;
+        if (per) {
+          da = d0[ia];
+          db = d0[ib];
+        } else {
+          da = ia <= n + 1 ? d0[ia] : -d0[M - ia];
+          db = ib <= n + 1 ? d0[ib] : -d0[M - ib];
+        }
+        d1[l] = d0[l] - g * (da + db);
+      }
+      __syncthreads();
+      double* t = d0;
+      d0 = d1;
+      d1 = t;
+    }
+    for (int l = l0 + threadIdx.x; l < l1; l += T) c.out[per ? l : l - 1] = d0[l] / L.divisor;
+    return;
+  }
+
+  // chunk mode: rows [g0, g0 + B) of the cycle plus a halo of H rows each side
+  const int B = L.B, H = L.H, E = B + 2 * H;
+  const int g0 = (per ? 0 : 1) + bk.chunk * B;
+  double* d0 = lds;
+  double* d1 = lds + E;
+  for (int l = threadIdx.x; l < E; l += T) {
+    int g = (g0 - H + l) % M;
+    if (g < 0) g += M;
+    d0[l] = rhs_ext(L, c, g);
+  }
+  __syncthreads();
+  const int K = L.stages;
+  for (int k = 0; k < K; ++k) {
+    const int sh = 1 << k;
+    const int reach = (1 << K) - (2 << k);            // rows beyond the chunk still needed
+    const int lo = H - reach, hi = H + B + reach;
+    const double g = L.gamma[k];
+    for (int l = lo + threadIdx.x; l < hi; l += T) d1[l] = d0[l] - g * (d0[l - sh] + d0[l + sh]);
+    __syncthreads();
+    double* t = d0;
+    d0 = d1;
+    d1 = t;
+  }
+  const int last = per ? n : n + 1;                   // one past the last physical row of g
+  for (int l = H + threadIdx.x; l < H + B; l += T) {
+    const int g = g0 - H + l;
+    if (g < last) c.out[per ? g : g - 1] = d0[l] / L.divisor;
+  }
+}
+
+__global__ void k_nonfinite(const double* __restrict__ x, int64_t count, int* flag) {
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    if (!(v - v == 0.0)) bad = 1;      // NaN or Inf
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+size_t lds_bytes_1d(const Lvl1D& it) {
+  if (it.wrap) {
+    const int ms = it.bc == RIDC_BC_PERIODIC ? it.n : it.n + 2;
+    return 2 * sizeof(double) * (size_t)ms;
+  }
+  return 2 * sizeof(double) * (size_t)(it.B + 2 * it.H);
+}
+
+template <int T>
+hipError_t allow_lds(size_t lds_bytes) {
+  static size_t allowed = 65536;
+  if (lds_bytes > allowed) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step1d<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    allowed = lds_bytes;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_1d_step(const Lvl1D* d_items, const Blk1D* d_blocks, int nblocks, int threads,
+                          size_t lds_bytes, int64_t sigma, hipStream_t stream) {
+  if (nblocks <= 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+  switch (threads) {
+    case 64: e = allow_lds<64>(lds_bytes); break;
+    case 128: e = allow_lds<128>(lds_bytes); break;
+    case 256: e = allow_lds<256>(lds_bytes); break;
+    case 512: e = allow_lds<512>(lds_bytes); break;
+    case 1024: e = allow_lds<1024>(lds_bytes); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  switch (threads) {
+    case 64:
+      hipLaunchKernelGGL(k_step1d<64>, dim3(nblocks), dim3(64), lds_bytes, stream, d_items,
+                         d_blocks, sigma);
+      break;
+    case 128:
+      hipLaunchKernelGGL(k_step1d<128>, dim3(nblocks), dim3(128), lds_bytes, stream, d_items,
+                         d_blocks, sigma);
+      break;
+    case 256:
+      hipLaunchKernelGGL(k_step1d<256>, dim3(nblocks), dim3(256), lds_bytes, stream, d_items,
+                         d_blocks, sigma);
+      break;
+    case 512:
+      hipLaunchKernelGGL(k_step1d<512>, dim3(nblocks), dim3(512), lds_bytes, stream, d_items,
+                         d_blocks, sigma);
+      break;
+    case 1024:
+      hipLaunchKernelGGL(k_step1d<1024>, dim3(nblocks), dim3(1024), lds_bytes, stream, d_items,
+                         d_blocks, sigma);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_check(const double* x, int64_t count, int* flag, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)blocks), dim3(256), 0, stream, x, count, flag);
+  return hipGetLastError();
+}
+
+}  // namespace ridc

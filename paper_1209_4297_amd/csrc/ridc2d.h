@@ -1,0 +1,25 @@
+// 2D (n x n Dirichlet) part of the RIDC library: fast-diagonalisation solves on MFMA.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ridc.h"
+
+namespace ridc {
+
+struct Plan2D;
+
+int plan2d_validate(const ridc_problem* p);
+size_t plan2d_workspace_bytes(const ridc_problem* p);
+int plan2d_create(const ridc_problem* p, double h, double* const* ring, const int* R,
+                  const double* W, const int64_t* woff, char* ws, size_t ws_bytes,
+                  hipStream_t stream, Plan2D** out);
+void plan2d_destroy(Plan2D* pl);
+int plan2d_arm(Plan2D* pl, int64_t nt, hipStream_t stream);
+// One pipeline step of each plan; sigma[i] is plan i's own pipeline step.
+int plan2d_step(Plan2D* const* pls, int count, const int64_t* sigma, hipStream_t stream);
+void plan2d_cost(const Plan2D* pl, double* bytes, double* flops);
+
+}  // namespace ridc

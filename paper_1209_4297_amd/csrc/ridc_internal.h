@@ -1,0 +1,94 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the RIDC library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "ridc.h"
+
+namespace ridc {
+
+constexpr int kMaxPcr = 48;          // PCR stages kept in a level descriptor
+constexpr int kMaxOrder = RIDC_MAX_ORDER;
+
+// ---------------------------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define RIDC_HIP_TRY(expr)                                                             \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return ::ridc::fail(RIDC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// plan helpers (plan.cpp)
+// ---------------------------------------------------------------------------------------------
+// Quadrature weights of corrector j, start-up row r, in units of dt (ascending nodes), from
+// exact rational arithmetic.
+bool quadrature_weights(int j, int r, double* out);
+
+// PCR plan for (I - r D2) on a cycle of length m: stage coefficients gamma_k = a_k / b_k,
+// the shift of each stage modulo m, and the final divisor.  `exact` is true when the stages end
+// with a diagonal system (2^K = 0 mod m) rather than a negligible coupling.
+struct PcrPlan {
+  int stages = 0;
+  bool exact = false;
+  double divisor = 1.0;
+  double gamma[kMaxPcr];
+  int64_t shift[kMaxPcr];
+};
+bool pcr_plan(double r, int64_t m, PcrPlan* out);
+
+// Ring slots of level j in a P-level pipeline: 2j+3 for j < P-1 (the live window that level
+// j+1 reads plus the slot being written), 2 for the top level.
+inline int ring_slots(int j, int P) { return j == P - 1 ? 2 : 2 * j + 3; }
+
+// ---------------------------------------------------------------------------------------------
+// 1D level-step descriptor: one (instance, level) work item, static for a handle
+// ---------------------------------------------------------------------------------------------
+struct Lvl1D {
+  double* own;             // ring of this level (R_own slots of n values)
+  const double* prev;      // ring of level j-1 (R_prev slots), null for j = 0
+  const double* W;         // weights of this level: j rows x (j+1), ascending nodes
+  int64_t nt;              // time steps of the integration
+  int64_t sigma0;          // pipeline step at which this instance's step 0 sits
+  int32_t n, j, R_own, R_prev;
+  int32_t bc, fe;          // ridc_bc, ridc_fe_kind
+  int32_t stages;          // PCR stages
+  int32_t wrap;            // 1: whole cycle in one workgroup; 0: chunk + halo
+  int32_t M;               // cycle length (periodic n, Dirichlet 2n+2)
+  int32_t B;               // rows per chunk (chunk mode)
+  int32_t H;               // halo rows each side (chunk mode) = 2^stages - 1
+  int32_t nchunks;
+  double dt;
+  double a_2h;             // a / (2h)
+  double nu_h2;            // nu / h^2
+  double divisor;          // final PCR divisor
+  double gamma[kMaxPcr];
+  int32_t shift[kMaxPcr];  // 2^k mod M
+};
+
+struct Blk1D {
+  int32_t item;
+  int32_t chunk;
+};
+
+// Launch one pipeline step of a grouped 1D batch.
+hipError_t launch_1d_step(const Lvl1D* d_items, const Blk1D* d_blocks, int nblocks, int threads,
+                          size_t lds_bytes, int64_t sigma, hipStream_t stream);
+
+// Set *flag to 1 if any of x[0..count) is not finite.
+hipError_t launch_nonfinite_check(const double* x, int64_t count, int* flag, hipStream_t stream);
+
+// LDS bytes a 1D item needs.
+size_t lds_bytes_1d(const Lvl1D& it);
+
+}  // namespace ridc

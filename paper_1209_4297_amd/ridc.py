@@ -1,0 +1,233 @@
+"""Thin ctypes binding of the RIDC C ABI (``include/ridc.h``).
+
+Argument marshalling only: every step of the integration runs in the HIP library.  Device
+arrays are torch CUDA float64 tensors; work runs on the current torch stream unless a stream
+is given.  There is no CPU fallback: importing this module raises if ``libridc.so`` is absent.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libridc.so")
+
+RIDC_OK = 0
+RIDC_E_INVAL = -1
+RIDC_E_UNSUPPORTED = -2
+RIDC_E_NOMEM = -3
+RIDC_E_HIP = -4
+RIDC_E_NONFINITE = -5
+RIDC_E_STATE = -6
+
+BC = {"periodic": 0, "dirichlet": 1}
+FE = {"none": 0, "advect": 1, "logistic": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+_ERR_NAMES = {-1: "RIDC_E_INVAL", -2: "RIDC_E_UNSUPPORTED", -3: "RIDC_E_NOMEM",
+              -4: "RIDC_E_HIP", -5: "RIDC_E_NONFINITE", -6: "RIDC_E_STATE"}
+
+
+class RidcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("bc", ctypes.c_int32), ("n", ctypes.c_int64),
+        ("length", ctypes.c_double), ("fe_kind", ctypes.c_int32), ("order", ctypes.c_int32),
+        ("a", ctypes.c_double), ("nu", ctypes.c_double), ("dt", ctypes.c_double),
+        ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"RIDC HIP library not built: {_LIB_PATH} is missing "
+                          "(run paper_1209_4297_amd/build.py)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    sig = {
+        "ridc_create": (ctypes.c_int, [ctypes.POINTER(Problem), vp, ctypes.POINTER(vp)]),
+        "ridc_destroy": (ctypes.c_int, [vp]),
+        "ridc_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(Problem)]),
+        "ridc_integrate": (ctypes.c_int, [vp, dp, i64, dp, dp]),
+        "ridc_integrate_batch": (ctypes.c_int, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
+                                                ctypes.POINTER(i64), ctypes.POINTER(vp)]),
+        "ridc_begin": (ctypes.c_int, [vp, dp, i64]),
+        "ridc_advance": (ctypes.c_int, [ctypes.POINTER(vp), i32, i64]),
+        "ridc_remaining": (i64, [vp]),
+        "ridc_read": (ctypes.c_int, [vp, dp, dp]),
+        "ridc_sync": (ctypes.c_int, [vp]),
+        "ridc_last_error": (ctypes.c_char_p, []),
+        "ridc_quadrature_weights": (ctypes.c_int, [i32, i32, ctypes.POINTER(ctypes.c_double)]),
+        "ridc_pcr_plan": (ctypes.c_int, [ctypes.c_double, i64, ctypes.POINTER(i32),
+                                         ctypes.POINTER(ctypes.c_double)]),
+        "ridc_step_cost": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]),
+        "ridc_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("ridc_create", "ridc_destroy", "ridc_footprint_bytes", "ridc_integrate",
+            "ridc_integrate_batch", "ridc_begin", "ridc_advance", "ridc_remaining", "ridc_read",
+            "ridc_sync", "ridc_last_error", "ridc_quadrature_weights", "ridc_pcr_plan",
+            "ridc_step_cost", "ridc_version")
+
+
+def lib():
+    return _lib
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _check(rc: int):
+    if rc != RIDC_OK:
+        raise RidcError(rc, _lib.ridc_last_error().decode())
+
+
+def make_problem(prob: dict, dt: float | None = None, prec: str = "fp64") -> Problem:
+    """ctypes ``ridc_problem`` from a workload dictionary (see ``workloads``)."""
+    if dt is None:
+        dt = float(prob["T"]) / int(prob["nt"])
+    return Problem(dim=int(prob["dim"]), bc=BC[prob["bc"]], n=int(prob["n"]),
+                   length=float(prob["length"]), fe_kind=FE[prob["fe"]],
+                   order=int(prob["order"]), a=float(prob.get("a", 0.0)),
+                   nu=float(prob["nu"]), dt=float(dt), prec=PREC[prec], reserved=0)
+
+
+def footprint_bytes(prob: dict, dt: float | None = None, prec: str = "fp64") -> int:
+    p = make_problem(prob, dt, prec)
+    return int(_lib.ridc_footprint_bytes(ctypes.byref(p)))
+
+
+def quadrature_weights(j: int, r: int):
+    out = (ctypes.c_double * (j + 1))()
+    _check(_lib.ridc_quadrature_weights(j, r, out))
+    return list(out)
+
+
+def pcr_plan(r: float, m: int):
+    st = ctypes.c_int32()
+    dv = ctypes.c_double()
+    _check(_lib.ridc_pcr_plan(r, m, ctypes.byref(st), ctypes.byref(dv)))
+    return st.value, dv.value
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise TypeError("device arrays must be contiguous float64 CUDA tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Ridc:
+    """One RIDC integrator instance (owns its device rings, transforms and workspaces)."""
+
+    def __init__(self, prob: dict, dt: float | None = None, prec: str = "fp64", stream=None):
+        self.prob = dict(prob)
+        self.prec = prec
+        self._p = make_problem(prob, dt, prec)
+        self.order = self._p.order
+        self.npts = self._p.n if self._p.dim == 1 else self._p.n * self._p.n
+        self._h = ctypes.c_void_p()
+        self._stream = stream
+        _check(_lib.ridc_create(ctypes.byref(self._p), _stream_ptr(stream),
+                                ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _lib.ridc_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def integrate(self, u0, nsteps: int, uT=None, levels=None, sync: bool = True):
+        import torch
+        if uT is None:
+            uT = torch.empty_like(u0)
+        _check(_lib.ridc_integrate(self._h, _ptr(u0), int(nsteps), _ptr(uT), _ptr(levels)))
+        if sync:
+            self.sync()
+        return uT
+
+    def begin(self, u0, nsteps: int):
+        _check(_lib.ridc_begin(self._h, _ptr(u0), int(nsteps)))
+
+    def remaining(self) -> int:
+        return int(_lib.ridc_remaining(self._h))
+
+    def read(self, uT, levels=None):
+        _check(_lib.ridc_read(self._h, _ptr(uT), _ptr(levels)))
+
+    def sync(self):
+        _check(_lib.ridc_sync(self._h))
+
+    def step_cost(self):
+        b = ctypes.c_double()
+        f = ctypes.c_double()
+        _check(_lib.ridc_step_cost(self._h, ctypes.byref(b), ctypes.byref(f)))
+        return b.value, f.value
+
+
+def _handle_array(solvers):
+    arr = (ctypes.c_void_p * len(solvers))()
+    for i, s in enumerate(solvers):
+        arr[i] = s.handle.value
+    return arr
+
+
+def advance(solvers, max_steps: int):
+    """Advance several instances together (grouped launches per pipeline step)."""
+    _check(_lib.ridc_advance(_handle_array(solvers), len(solvers), int(max_steps)))
+
+
+def integrate_batch(solvers, u0s, nsteps, uTs):
+    n = len(solvers)
+    u0a = (ctypes.c_void_p * n)(*[t.data_ptr() for t in u0s])
+    uTa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in uTs])
+    nsa = (ctypes.c_int64 * n)(*[int(x) for x in nsteps])
+    _check(_lib.ridc_integrate_batch(_handle_array(solvers), n, u0a, nsa, uTa))
+
+
+def pipeline_steps(nt: int, order: int) -> int:
+    return nt + order * (order - 1) // 2 if nt > 0 else 0
+
+
+def grid_h(prob: dict) -> float:
+    n = int(prob["n"])
+    return prob["length"] / n if prob["bc"] == "periodic" else prob["length"] / (n + 1)
+
+
+__all__ = ["Ridc", "RidcError", "advance", "integrate_batch", "make_problem", "footprint_bytes",
+           "quadrature_weights", "pcr_plan", "pipeline_steps", "library_path", "lib", "EXPORTED",
+           "math"]

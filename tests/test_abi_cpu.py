@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI library (no GPU work): it loads, exports every declared entry
+point, and its host plan (exact weights, PCR stage plan, footprints) is right."""
+import math
+import os
+import re
+from fractions import Fraction
+
+import pytest
+
+from oracle import lagrange_integral_weights
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ridc():
+    from paper_1209_4297_amd import ridc as mod
+    return mod
+
+
+def test_header_symbols_are_exported(ridc):
+    text = open(os.path.join(ROOT, "include", "ridc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(ridc_[a-z_0-9]+)\s*\(", text))
+    assert len(names) >= 15
+    for name in sorted(names):
+        assert hasattr(ridc.lib(), name), name
+    assert set(ridc.EXPORTED) == names
+
+
+@pytest.mark.parametrize("j", range(1, 12))
+def test_library_weights_are_correctly_rounded(ridc, j):
+    for r in range(j):
+        exact = lagrange_integral_weights(list(range(j + 1)), r, r + 1)
+        got = ridc.quadrature_weights(j, r)
+        assert got == [float(x) for x in exact], (j, r)
+
+
+def test_weights_reject_bad_rows(ridc):
+    with pytest.raises(ridc.RidcError):
+        ridc.quadrature_weights(3, 3)
+    with pytest.raises(ridc.RidcError):
+        ridc.quadrature_weights(0, 0)
+
+
+def _dense_cyclic_solve_check(r, m, stages, divisor):
+    """Apply the PCR plan's stage recursion in exact-ish float arithmetic to a cyclic system and
+    compare with a dense solve (numpy), for small m."""
+    import numpy as np
+    a = np.zeros((m, m))
+    for i in range(m):
+        a[i, i] += 1 + 2 * r
+        a[i, (i - 1) % m] += -r
+        a[i, (i + 1) % m] += -r
+    d = np.random.default_rng(m).standard_normal(m)
+    x_ref = np.linalg.solve(a, d)
+    # replay the stages: coefficients b, c of the cyclic system with stride s
+    b, c = 1 + 2 * r, -r
+    s = 1
+    for _ in range(stages):
+        g = c / b
+        d = d - g * (np.roll(d, s) + np.roll(d, -s))
+        b, c = b - 2 * c * c / b, -c * c / b
+        s = (2 * s) % m
+    x = d / divisor
+    return np.max(np.abs(x - x_ref)) / np.max(np.abs(x_ref))
+
+
+@pytest.mark.parametrize("r,m", [(0.2, 128), (33.6, 16386), (1e4, 64), (1e4, 100), (0.0, 10),
+                                 (5.0, 2), (3.0, 7), (1e6, 1000)])
+def test_pcr_plan(ridc, r, m):
+    stages, divisor = ridc.pcr_plan(r, m)
+    if r == 0:
+        assert stages == 0 and divisor == 1.0
+        return
+    if m <= 2000:
+        # both solves lose accuracy with the condition number 1 + 4r
+        assert _dense_cyclic_solve_check(r, m, stages, divisor) < 1e-14 * (10 + 4 * r)
+    # a system whose coupling decays fast needs few stages
+    if r < 1:
+        assert stages <= 8
+
+
+def test_footprint(ridc):
+    import workloads
+    prob, _ = workloads.config_reacdiff_1d()
+    fp = ridc.footprint_bytes(prob)
+    # 17 ring slots of 8192 doubles for order 4 (3 + 5 + 7 + 2), plus small tables
+    assert 17 * 8192 * 8 <= fp < 17 * 8192 * 8 + 64 * 1024
+    bad = dict(prob, n=1)
+    assert ridc.footprint_bytes(bad) == 0

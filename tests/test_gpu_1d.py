@@ -1,0 +1,205 @@
+"""GPU parity of the 1D RIDC path (fused level-step + PCR in LDS) against the FP64 oracle.
+
+Bar: relative L2 <= 1e-12 per level against the oracle on the same seeded inputs (both FP64; the
+GPU contracts to FMA and solves by PCR, the oracle solves by FFT or banded LU, so only rounding
+differs).  Tiling, batching, graph replay and repetition must not change a single bit.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import Problem, rel_l2, ridc_pipelined
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1209_4297_amd import ridc
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, ridc
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(env, prob, u0, nt=None, levels=True, prec="fp64"):
+    torch, ridc = env
+    nt = prob["nt"] if nt is None else nt
+    dt = prob["T"] / prob["nt"]
+    s = ridc.Ridc(prob, dt=dt, prec=prec)
+    x0 = torch.tensor(np.asarray(u0), dtype=torch.float64, device="cuda").reshape(-1)
+    uT = torch.empty_like(x0)
+    lv = torch.empty(prob["order"] * x0.numel(), dtype=torch.float64, device="cuda") if levels else None
+    s.integrate(x0, nt, uT, lv)
+    out = uT.cpu().numpy()
+    lvs = lv.cpu().numpy().reshape(prob["order"], -1) if levels else None
+    s.close()
+    return out, lvs
+
+
+def check_against_oracle(env, prob, u0, nt=None, tol=TOL):
+    nt = prob["nt"] if nt is None else nt
+    _say(f"case: {prob['dim']}D {prob['bc']} n={prob['n']} P={prob['order']} nt={nt} fe={prob['fe']}")
+    p = Problem(dim=prob["dim"], bc=prob["bc"], n=prob["n"], length=prob["length"], fe=prob["fe"],
+                a=prob.get("a", 0.0), nu=prob["nu"], dt=prob["T"] / prob["nt"])
+    ref = ridc_pipelined(p, np.asarray(u0), nt, prob["order"])
+    top, lvs = run_gpu(env, prob, u0, nt)
+    for j in range(prob["order"]):
+        err = rel_l2(lvs[j], ref[j]) if np.linalg.norm(ref[j]) > 0 else np.abs(lvs[j]).max()
+        assert err <= tol, (j, err)
+    np.testing.assert_array_equal(top, lvs[-1])
+    return ref, top
+
+
+def test_advdiff_n128_full(env):
+    prob, u0 = workloads.config_advdiff_1d()
+    ref, top = check_against_oracle(env, prob, u0)
+    # and it is a fourth-order accurate answer to the semi-discrete problem (sanity)
+    h = 2 * math.pi / 128
+    lam = -1j * math.sin(h) / h - (4 * 0.1 / h**2) * math.sin(h / 2) ** 2
+    x = np.arange(128) * h
+    exact = np.imag(np.exp(lam) * np.exp(1j * x))
+    assert rel_l2(top, exact) < 1e-9
+
+
+def test_reacdiff_n8192_full(env):
+    prob, u0 = workloads.config_reacdiff_1d()
+    check_against_oracle(env, prob, u0)
+
+
+def test_reacdiff_chunked_ragged(env):
+    # n = 3000 with r = 4.5: few PCR stages, so chunks of 1024 rows (ragged last chunk)
+    prob, u0 = workloads.config_reacdiff_1d(n=3000, nt=400, T=0.2)
+    check_against_oracle(env, prob, u0)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 5, 6])
+def test_orders(env, order):
+    prob, u0 = workloads.config_advdiff_1d(n=96, nt=40, order=order, T=0.4)
+    check_against_oracle(env, prob, u0)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_minimum_steps(env, order):
+    prob, u0 = workloads.config_reacdiff_1d(n=64, nt=order - 1, order=order, T=0.01)
+    check_against_oracle(env, prob, u0)
+
+
+def test_zero_steps_returns_u0(env):
+    prob, u0 = workloads.config_advdiff_1d(n=32, nt=10)
+    top, lvs = run_gpu(env, prob, u0, nt=0)
+    np.testing.assert_array_equal(top, u0)
+    for j in range(prob["order"]):
+        np.testing.assert_array_equal(lvs[j], u0)
+
+
+@pytest.mark.parametrize("bc,n,fe,nu,T,nt", [
+    ("periodic", 2, "advect", 0.5, 1.0, 20),      # smallest periodic cycle
+    ("dirichlet", 2, "logistic", 0.1, 1.0, 20),
+    ("periodic", 100, "advect", 0.05, 1.0, 50),   # non-power-of-two cycle, threshold plan
+    ("periodic", 64, "none", 5.0, 1.0, 10),       # huge r: exact plan down to the 2x2 end
+    ("dirichlet", 777, "advect", 1e-2, 0.5, 60),  # advection with zero ghosts
+    ("dirichlet", 5000, "none", 1e-3, 1.0, 20),   # r = 1250, wrap mode on the odd extension
+    ("periodic", 4096, "advect", 1e-3, 0.25, 200),
+])
+def test_edge_grids(env, bc, n, fe, nu, T, nt):
+    length = 2 * math.pi if bc == "periodic" else 1.0
+    x = workloads.grid_points(bc, n, length)
+    u0 = np.sin(x) + 0.5 * np.cos(3 * x) + (0.3 if bc == "periodic" else 0.0)
+    if bc == "dirichlet":
+        u0 = np.clip(x * (length - x) * 3, 0, 1) + 0.1 * np.sin(7 * x)
+    prob = dict(dim=1, bc=bc, n=n, length=length, fe=fe, a=0.8, nu=nu, T=T, nt=nt, order=4)
+    check_against_oracle(env, prob, u0)
+
+
+def test_batch_bitwise_equals_solo(env):
+    torch, ridc = env
+    cases = workloads.config_batched_1d(count=12, nt=120, T=0.03)
+    solvers, u0s, uTs, solo = [], [], [], []
+    for prob, u0 in cases:
+        s = ridc.Ridc(prob)
+        x0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+        solo.append(s.integrate(x0, prob["nt"]).cpu().numpy())
+        solvers.append(s)
+        u0s.append(x0)
+        uTs.append(torch.empty_like(x0))
+    # mix in a Dirichlet reaction-diffusion instance of another order
+    prob2, u02 = workloads.config_reacdiff_1d(n=2500, nt=90, order=3, T=0.05)
+    s2 = ridc.Ridc(prob2)
+    x2 = torch.tensor(u02, dtype=torch.float64, device="cuda")
+    solo.append(s2.integrate(x2, prob2["nt"]).cpu().numpy())
+    solvers.append(s2)
+    u0s.append(x2)
+    uTs.append(torch.empty_like(x2))
+    nts = [p["nt"] for p, _ in cases] + [prob2["nt"]]
+    ridc.integrate_batch(solvers, u0s, nts, uTs)
+    torch.cuda.synchronize()
+    for i, uT in enumerate(uTs):
+        np.testing.assert_array_equal(uT.cpu().numpy(), solo[i])
+    # stepping interface with uneven chunks gives the same bits too
+    for s, x0, prob_nt in zip(solvers, u0s, nts):
+        s.begin(x0, prob_nt)
+    while any(s.remaining() > 0 for s in solvers):
+        ridc.advance(solvers, 37)
+    for i, s in enumerate(solvers):
+        out = torch.empty_like(u0s[i])
+        s.read(out)
+        s.sync()
+        np.testing.assert_array_equal(out.cpu().numpy(), solo[i])
+    for s in solvers:
+        s.close()
+
+
+def test_graph_and_direct_launch_agree(env, monkeypatch):
+    prob, u0 = workloads.config_reacdiff_1d(n=2048, nt=300, T=0.15)
+    a, _ = run_gpu(env, prob, u0, levels=False)
+    b, _ = run_gpu(env, prob, u0, levels=False)
+    monkeypatch.setenv("RIDC_GRAPH", "0")
+    c, _ = run_gpu(env, prob, u0, levels=False)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, c)
+
+
+def test_nonfinite_is_reported(env):
+    torch, ridc = env
+    prob, u0 = workloads.config_advdiff_1d(n=64, nt=20)
+    u0 = u0.copy()
+    u0[5] = np.nan
+    s = ridc.Ridc(prob)
+    x0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    with pytest.raises(ridc.RidcError) as ei:
+        s.integrate(x0, 20)
+    assert ei.value.code == ridc.RIDC_E_NONFINITE
+    # the handle stays usable
+    out = s.integrate(torch.tensor(workloads.config_advdiff_1d(n=64, nt=20)[1], dtype=torch.float64,
+                                   device="cuda"), 20)
+    assert torch.isfinite(out).all()
+    s.close()
+
+
+def test_state_errors(env):
+    torch, ridc = env
+    prob, u0 = workloads.config_advdiff_1d(n=64, nt=20)
+    s = ridc.Ridc(prob)
+    x0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(x0)
+    with pytest.raises(ridc.RidcError) as ei:
+        s.read(out)
+    assert ei.value.code == ridc.RIDC_E_STATE
+    s.begin(x0, 20)
+    assert s.remaining() == 20 + 6
+    with pytest.raises(ridc.RidcError):
+        s.read(out)
+    with pytest.raises(ridc.RidcError) as ei:
+        s.begin(x0, 2)                      # below order - 1
+    assert ei.value.code == ridc.RIDC_E_INVAL
+    s.close()

@@ -111,3 +111,39 @@ def test_solve_on_modes_closed_form():
     eig2 = 1 + p2.dt * (4 * p2.nu / p2.h**2) * (math.sin(3 * math.pi * p2.h / 2) ** 2
                                                 + math.sin(5 * math.pi * p2.h / 2) ** 2)
     np.testing.assert_allclose(solve_implicit(p2, v2), v2 / eig2, atol=1e-13)
+
+
+def _thomas_longdouble(r, rhs):
+    """Tridiagonal (Dirichlet) solve of (1+2r) x_i - r x_{i-1} - r x_{i+1} = rhs_i in long
+    double (64-bit mantissa), by the Thomas algorithm."""
+    n = len(rhs)
+    ld = np.longdouble
+    b = ld(1) + 2 * ld(r)
+    a = -ld(r)
+    cp = [ld(0)] * n
+    dp = [ld(0)] * n
+    cp[0] = a / b
+    dp[0] = ld(rhs[0]) / b
+    for i in range(1, n):
+        den = b - a * cp[i - 1]
+        cp[i] = a / den
+        dp[i] = (ld(rhs[i]) - a * dp[i - 1]) / den
+    x = [ld(0)] * n
+    x[-1] = dp[-1]
+    for i in range(n - 2, -1, -1):
+        x[i] = dp[i] - cp[i] * x[i + 1]
+    return np.array(x, dtype=np.longdouble)
+
+
+@pytest.mark.parametrize("r,bound", [(0.3, 1e-15), (33.6, 1.5e-15), (2.5e3, 5e-15)])
+def test_dirichlet_solve_is_accurate_to_rounding(r, bound):
+    """The refined oracle solve sits within a few ulps (growing slowly with the condition
+    number 1 + 4r) of a long-double Thomas solve."""
+    n = 1024
+    p = _prob(1, "dirichlet", n, nu=1.0, dt=r / (n + 1) ** 2)
+    assert abs(p.dt * p.nu / p.h**2 - r) < 1e-9 * r
+    rhs = np.random.default_rng(7).uniform(0.0, 1.0, n)
+    x = solve_implicit(p, rhs)
+    ref = _thomas_longdouble(p.dt * p.nu / p.h**2, rhs)
+    err = np.max(np.abs(x - ref.astype(np.float64))) / np.max(np.abs(ref.astype(np.float64)))
+    assert err < bound, err
