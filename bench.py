@@ -78,6 +78,7 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     solver = ridc.Ridc(prob)
+    tile = solver.autotune()                 # result-neutral tiling choice, measured
     x0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
     uT = torch.empty_like(x0)
 
@@ -143,6 +144,7 @@ def main():
                                "N=8192, nu=1e-3, 8 seeded Gaussians, RIDC order 4, T=1, "
                                "Nt=2000, FP64",
                    "n": n, "nt": nt, "order": P, "pipeline_steps": nt + P * (P - 1) // 2,
+                   "tile": {"threads": tile[0], "rows": tile[1]},
                    "parallelism": "single GPU"},
         "rel_l2_vs_oracle": rel,
         "roofline": roofline,

@@ -152,6 +152,20 @@ int ridc_pcr_plan(double r, int64_t m, int32_t* stages, double* divisor);
  * per pipeline step at steady state (1D) or flops per step of the 2D transforms.             */
 int ridc_step_cost(const ridc_handle* h, double* hbm_bytes, double* flops);
 
+/* ---- tuning --------------------------------------------------------------------------------- */
+/* Measure candidate 1D tilings (threads per workgroup; whole cycle per workgroup, or chunks of
+ * `rows` rows with a PCR halo) on the handle's stream and keep the fastest for this handle and
+ * for later handles with the same (n, boundary, PCR stages).  Every tiling performs the same
+ * operations for every output value, so results are bitwise independent of the choice.  The
+ * tuning steps overwrite the level rings: the handle must be re-armed (ridc_begin) afterwards.
+ * threads_out/rows_out (nullable) receive the choice (rows 0 = whole cycle).  2D: no-op.     */
+int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out);
+
+/* Force a 1D tiling: threads in {64,128,256,512,1024}; rows = 0 for the whole cycle in one
+ * workgroup, else chunks of `rows` rows (allowed when the PCR coupling vanishes within a halo
+ * shorter than the system).  Errors: RIDC_E_INVAL if the tiling does not fit.                 */
+int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows);
+
 /* Library version string.                                                                     */
 const char* ridc_version(void);
 

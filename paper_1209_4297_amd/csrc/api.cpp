@@ -59,6 +59,7 @@ struct ridc_handle {
   std::vector<Blk1D> blocks;  // blocks of a solo launch
   Lvl1D* d_items = nullptr;   // device copies (inside the pool)
   Blk1D* d_blocks = nullptr;
+  size_t blocks_cap = 0;
   size_t lds = 0;
 
   // 2D plan
@@ -164,7 +165,7 @@ bool tile_fits(const ridc_problem* p, const PcrPlan& pcr, const Tile1D& t) {
     return false;
   if (t.wrap) return 2 * sizeof(double) * (size_t)ms <= (size_t)device_max_lds();
   const int64_t H = halo_rows(pcr);
-  if (pcr.exact || H >= M || t.B < 1) return false;
+  if (pcr.exact || H >= M || t.B < 1 || t.B + H > p->n) return false;
   return 2 * sizeof(double) * (size_t)(t.B + 2 * H) <= (size_t)device_max_lds();
 }
 
@@ -204,6 +205,8 @@ int plan_1d(const ridc_problem* p, PcrPlan* pcr, Tile1D* tile) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int kMinChunk = 128;
+
 struct Layout {
   size_t rings = 0, weights = 0, flag = 0, items = 0, blocks = 0, ws2d = 0, total = 0;
   int64_t nblocks = 0;
@@ -220,7 +223,9 @@ void plan_layout(const ridc_problem* p, const Tile1D* tile, Layout* L) {
   L->weights = align256(sizeof(double) * (size_t)std::max<int64_t>(nw, 1));
   L->flag = 256;
   if (p->dim == 1) {
-    const int64_t nchunks = tile->wrap ? 1 : (p->n + tile->B - 1) / tile->B;
+    // room for the finest tiling the autotuner may pick (chunks of kMinChunk rows)
+    const int64_t nchunks = std::max<int64_t>(tile->wrap ? 1 : (p->n + tile->B - 1) / tile->B,
+                                              (p->n + kMinChunk - 1) / kMinChunk);
     L->nblocks = nchunks * P;
     L->items = align256(sizeof(Lvl1D) * P);
     L->blocks = align256(sizeof(Blk1D) * (size_t)L->nblocks);
@@ -365,6 +370,48 @@ int check_handles(ridc_handle* const* hs, int32_t count) {
   return RIDC_OK;
 }
 
+int apply_tile_1d(ridc_handle* h, const Tile1D& t) {
+  if (!tile_fits(&h->p, h->pcr, t)) return fail(RIDC_E_INVAL, "tile does not fit this system");
+  const size_t nchunks = t.wrap ? 1 : (size_t)((h->p.n + t.B - 1) / t.B);
+  if (nchunks * h->P > h->blocks_cap) return fail(RIDC_E_INVAL, "tile finer than the minimum chunk");
+  build_items_1d(h, t);
+  RIDC_HIP_TRY(hipMemcpyAsync(h->d_blocks, h->blocks.data(), sizeof(Blk1D) * h->blocks.size(),
+                              hipMemcpyHostToDevice, h->stream));
+  for (auto& it : h->proto) it.nt = h->nt < 0 ? 0 : h->nt;
+  RIDC_HIP_TRY(hipMemcpyAsync(h->d_items, h->proto.data(), sizeof(Lvl1D) * h->proto.size(),
+                              hipMemcpyHostToDevice, h->stream));
+  RIDC_HIP_TRY(hipStreamSynchronize(h->stream));   // the host tables are rebuilt by later calls
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  h->graph_nt = -1;
+  return RIDC_OK;
+}
+
+// Time `reps` steady-state steps of the handle with tile t (the rings hold zeros).
+int time_tile_1d(ridc_handle* h, const Tile1D& t, int reps, float* ms) {
+  int rc = apply_tile_1d(h, t);
+  if (rc != RIDC_OK) return rc;
+  for (auto& it : h->proto) it.nt = (int64_t)1 << 40;
+  RIDC_HIP_TRY(hipMemcpyAsync(h->d_items, h->proto.data(), sizeof(Lvl1D) * h->proto.size(),
+                              hipMemcpyHostToDevice, h->stream));
+  hipEvent_t a, b;
+  RIDC_HIP_TRY(hipEventCreate(&a));
+  RIDC_HIP_TRY(hipEventCreate(&b));
+  const int64_t first = (int64_t)h->P * (h->P - 1) / 2 + 1;   // every level active
+  rc = launch_solo_steps_1d(h, first, first + 4);               // warm-up
+  if (rc == RIDC_OK) {
+    (void)hipEventRecord(a, h->stream);
+    rc = launch_solo_steps_1d(h, first + 5, first + 4 + reps);
+    (void)hipEventRecord(b, h->stream);
+  }
+  if (rc == RIDC_OK && hipEventSynchronize(b) == hipSuccess) (void)hipEventElapsedTime(ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -475,6 +522,7 @@ int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out) {
     cur += L.items;
     h->d_blocks = (Blk1D*)cur;
     cur += L.blocks;
+    h->blocks_cap = (size_t)L.nblocks;
     build_items_1d(h, tile);
     if (hipMemcpy(h->d_blocks, h->blocks.data(), sizeof(Blk1D) * h->blocks.size(),
                   hipMemcpyHostToDevice) != hipSuccess) {
@@ -689,6 +737,63 @@ int ridc_integrate_batch(ridc_handle* const* hs, int32_t count, const double* co
     rc = ridc_read(hs[i], uT[i], nullptr);
     if (rc != RIDC_OK) return rc;
   }
+  return RIDC_OK;
+}
+
+int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows) {
+  if (!h) return fail(RIDC_E_INVAL, "NULL handle");
+  if (h->p.dim != 1) return fail(RIDC_E_UNSUPPORTED, "tiles are chosen per system in 1D only");
+  Tile1D t{rows == 0 ? 1 : 0, rows, threads};
+  return apply_tile_1d(h, t);
+}
+
+int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out) {
+  if (!h) return fail(RIDC_E_INVAL, "NULL handle");
+  if (h->p.dim != 1) {
+    if (threads_out) *threads_out = 256;
+    if (rows_out) *rows_out = 128;
+    return RIDC_OK;                      // 2D launch shapes are fixed per precision
+  }
+  const size_t ring_bytes = 0;
+  (void)ring_bytes;
+  // the tuning steps overwrite the rings: start from zeros, leave the handle unarmed
+  int64_t slots = 0;
+  for (int j = 0; j < h->P; ++j) slots += h->R[j];
+  RIDC_HIP_TRY(hipMemsetAsync(h->ring[0], 0, sizeof(double) * (size_t)(slots * h->npts), h->stream));
+  std::vector<Tile1D> cands;
+  for (int T : {256, 512, 1024}) {
+    cands.push_back(Tile1D{1, 0, T});
+    for (int B : {kMinChunk, 256, 512, 1024, 2048, 4096}) cands.push_back(Tile1D{0, B, T});
+  }
+  Tile1D best{};
+  float best_ms = 1e30f;
+  for (const Tile1D& t : cands) {
+    if (!tile_fits(&h->p, h->pcr, t)) continue;
+    float ms = 0;
+    int rc = time_tile_1d(h, t, 40, &ms);
+    if (rc != RIDC_OK) return rc;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  if (best_ms >= 1e29f) return fail(RIDC_E_UNSUPPORTED, "no tile fits");
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    bool found = false;
+    for (auto& e : g_tuned)
+      if (e.first.n == h->p.n && e.first.bc == h->p.bc && e.first.stages == h->pcr.stages) {
+        e.second = best;
+        found = true;
+      }
+    if (!found) g_tuned.push_back({TuneKey{h->p.n, h->p.bc, h->pcr.stages}, best});
+  }
+  h->nt = -1;
+  h->sigma = h->total = 0;
+  int rc = apply_tile_1d(h, best);
+  if (rc != RIDC_OK) return rc;
+  if (threads_out) *threads_out = best.threads;
+  if (rows_out) *rows_out = best.wrap ? 0 : best.B;
   return RIDC_OK;
 }
 

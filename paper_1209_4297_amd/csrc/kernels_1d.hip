@@ -41,84 +41,110 @@ __device__ __forceinline__ double at(const double* __restrict__ v, int p, int n,
   return v[p];
 }
 
-struct Ctx {
-  const double* u;     // eta[j]_n
-  double* out;         // slot of eta[j]_{n+1}
-  const double* w;     // weights row (j >= 1)
-  int64_t nidx;        // n
-  int64_t s;           // first window node
+// Per-workgroup view of one level step of level J: where the level's value and the previous
+// level's window live this step, and the coefficients that fold eq. (corr) into one sum over the
+// window:
+//   rhs = u + dt f_E(u) + sum_i [ cf_i f_E(v_i) + cl_i L v_i ]
+// with v_i = eta[J-1]_{s+i}, cf_i = dt (w_i - [s+i == n]), cl_i = dt (w_i - [s+i == n+1]).
+// J is a template parameter so the window lives in registers.
+template <int J>
+struct Step {
+  const double* u;
+  double* out;
+  const double* v[J + 1];
+  double cf[J + 1], cl[J + 1];
 };
 
-// Right-hand side of the level-j step at physical row p.
-__device__ __forceinline__ double rhs_at(const Lvl1D& L, const Ctx& c, int p) {
-  const int n = L.n;
-  const bool per = L.bc == RIDC_BC_PERIODIC;
-  const double um = at(c.u, p - 1, n, per);
-  const double u0 = c.u[p];
-  const double up = at(c.u, p + 1, n, per);
-  const double fe_u = fe_eval(L.fe, L.a_2h, um, u0, up);
-  if (L.j == 0) return u0 + L.dt * fe_u;
-  double quad = 0.0, fe_n = 0.0, li_n1 = 0.0;
-  for (int i = 0; i <= L.j; ++i) {
-    const int64_t node = c.s + i;
-    const double* v = L.prev + (node % L.R_prev) * (int64_t)n;
-    const double vm = at(v, p - 1, n, per);
-    const double v0 = v[p];
-    const double vp = at(v, p + 1, n, per);
-    const double li = L.nu_h2 * ((vm + vp) - 2.0 * v0);
-    const double fe = fe_eval(L.fe, L.a_2h, vm, v0, vp);
-    quad += c.w[i] * (fe + li);
-    if (node == c.nidx) fe_n = fe;
-    if (node == c.nidx + 1) li_n1 = li;
+struct Geo {        // scalar problem data of a work item, copied out of the descriptor
+  int n, M, fe;
+  bool per;
+  double dt, a_2h, nu_h2;
+};
+
+template <int J>
+__device__ __forceinline__ double rhs_row(const Geo& G, const Step<J>& S, int p) {
+  const int n = G.n;
+  const double u0 = S.u[p];
+  double um = 0.0, up = 0.0;
+  if (G.fe == RIDC_FE_ADVECT_C2) {
+    um = at(S.u, p - 1, n, G.per);
+    up = at(S.u, p + 1, n, G.per);
   }
-  return u0 + L.dt * fe_u - L.dt * (li_n1 + fe_n) + L.dt * quad;
+  double acc = u0 + G.dt * fe_eval(G.fe, G.a_2h, um, u0, up);
+  if constexpr (J > 0) {
+#pragma unroll
+    for (int i = 0; i <= J; ++i) {
+      const double* v = S.v[i];
+      const double vm = at(v, p - 1, n, G.per);
+      const double v0 = v[p];
+      const double vp = at(v, p + 1, n, G.per);
+      const double li = G.nu_h2 * ((vm + vp) - 2.0 * v0);
+      acc += S.cf[i] * fe_eval(G.fe, G.a_2h, vm, v0, vp) + S.cl[i] * li;
+    }
+  }
+  return acc;
 }
 
-// Right-hand side of row g of the odd/periodic extension (g in [0, M)).
-__device__ __forceinline__ double rhs_ext(const Lvl1D& L, const Ctx& c, int g) {
-  if (L.bc == RIDC_BC_PERIODIC) return rhs_at(L, c, g);
-  const int n = L.n;
-  if (g == 0 || g == n + 1) return 0.0;
-  if (g <= n) return rhs_at(L, c, g - 1);
-  return -rhs_at(L, c, L.M - g - 1);
+// Right-hand side of row g of the odd (Dirichlet) or periodic cycle, g in [0, M).
+template <int J>
+__device__ __forceinline__ double rhs_ext(const Geo& G, const Step<J>& S, int g) {
+  if (G.per) return rhs_row<J>(G, S, g);
+  if (g == 0 || g == G.n + 1) return 0.0;
+  if (g <= G.n) return rhs_row<J>(G, S, g - 1);
+  return -rhs_row<J>(G, S, G.M - g - 1);
 }
 
-template <int T>
-__global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
-                                              const Blk1D* __restrict__ blocks, int64_t sigma) {
-  extern __shared__ double lds[];
-  const Blk1D bk = blocks[blockIdx.x];
-  const Lvl1D& L = items[bk.item];
-  const int j = L.j;
-  const int64_t m = sigma - L.sigma0 - (int64_t)j * (j + 1) / 2;   // time index computed now
-  if (m < 1 || m > L.nt) return;                                    // level idle this step
-  const int n = L.n;
-  Ctx c;
-  c.nidx = m - 1;
-  c.u = L.own + (c.nidx % L.R_own) * (int64_t)n;
-  c.out = L.own + (m % L.R_own) * (int64_t)n;
-  c.s = 0;
-  c.w = nullptr;
-  if (j > 0) {
-    c.s = m - j > 0 ? m - j : 0;                      // window t_s..t_{s+j}
-    c.w = L.W + (c.nidx - c.s) * (j + 1);             // row r = n - s
+template <int J, int T>
+__device__ __forceinline__ void level_step(const Lvl1D* __restrict__ Lp, int chunk, int64_t m,
+                                           double* lds) {
+  const Lvl1D& L = *Lp;
+  Geo G;
+  G.n = L.n;
+  G.M = L.M;
+  G.fe = L.fe;
+  G.per = L.bc == RIDC_BC_PERIODIC;
+  G.dt = L.dt;
+  G.a_2h = L.a_2h;
+  G.nu_h2 = L.nu_h2;
+  const int n = G.n, M = G.M;
+  const bool per = G.per;
+  const int64_t nidx = m - 1;
+  Step<J> S;
+  S.u = L.own + (nidx % L.R_own) * (int64_t)n;
+  S.out = L.own + (m % L.R_own) * (int64_t)n;
+  if constexpr (J > 0) {
+    const int64_t s = m - J > 0 ? m - J : 0;          // window t_s..t_{s+J}
+    const double* w = L.W + (nidx - s) * (J + 1);     // row r = n - s
+    const int R = L.R_prev;
+    int slot = (int)(s % R);
+#pragma unroll
+    for (int i = 0; i <= J; ++i) {
+      S.v[i] = L.prev + (int64_t)slot * n;
+      slot = slot + 1 == R ? 0 : slot + 1;
+      const int64_t node = s + i;
+      const double wi = w[i];
+      S.cf[i] = G.dt * (wi - (node == nidx ? 1.0 : 0.0));
+      S.cl[i] = G.dt * (wi - (node == nidx + 1 ? 1.0 : 0.0));
+    }
   }
-  const bool per = L.bc == RIDC_BC_PERIODIC;
-  const int M = L.M;
+  const int stages = L.stages;
+  const double divisor = L.divisor;
+  const double* __restrict__ gam = L.gamma;
 
   if (L.wrap) {
     const int ms = per ? n : n + 2;                   // stored rows of the cycle
+    const int* __restrict__ shift = L.shift;
     double* d0 = lds;
     double* d1 = lds + ms;
     for (int l = threadIdx.x; l < ms; l += T) {
-      d0[l] = rhs_ext(L, c, l);
+      d0[l] = rhs_ext<J>(G, S, l);
       d1[l] = 0.0;
     }
     __syncthreads();
     const int l0 = per ? 0 : 1, l1 = per ? n : n + 1;  // Dirichlet ghosts stay zero
-    for (int k = 0; k < L.stages; ++k) {
-      const int sh = L.shift[k];
-      const double g = L.gamma[k];
+    for (int k = 0; k < stages; ++k) {
+      const int sh = shift[k];
+      const double g = gam[k];
       for (int l = l0 + threadIdx.x; l < l1; l += T) {
         int ia = l - sh;
         if (ia < 0) ia += M;
@@ -139,27 +165,27 @@ __global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
       d0 = d1;
       d1 = t;
     }
-    for (int l = l0 + threadIdx.x; l < l1; l += T) c.out[per ? l : l - 1] = d0[l] / L.divisor;
+    for (int l = l0 + threadIdx.x; l < l1; l += T) S.out[per ? l : l - 1] = d0[l] / divisor;
     return;
   }
 
   // chunk mode: rows [g0, g0 + B) of the cycle plus a halo of H rows each side
   const int B = L.B, H = L.H, E = B + 2 * H;
-  const int g0 = (per ? 0 : 1) + bk.chunk * B;
+  const int g0 = (per ? 0 : 1) + chunk * B;
   double* d0 = lds;
   double* d1 = lds + E;
   for (int l = threadIdx.x; l < E; l += T) {
-    int g = (g0 - H + l) % M;
+    int g = g0 - H + l;                               // in (-M, 2M): H < M, B + H <= n
     if (g < 0) g += M;
-    d0[l] = rhs_ext(L, c, g);
+    if (g >= M) g -= M;
+    d0[l] = rhs_ext<J>(G, S, g);
   }
   __syncthreads();
-  const int K = L.stages;
-  for (int k = 0; k < K; ++k) {
+  for (int k = 0; k < stages; ++k) {
     const int sh = 1 << k;
-    const int reach = (1 << K) - (2 << k);            // rows beyond the chunk still needed
+    const int reach = (1 << stages) - (2 << k);       // rows beyond the chunk still needed
     const int lo = H - reach, hi = H + B + reach;
-    const double g = L.gamma[k];
+    const double g = gam[k];
     for (int l = lo + threadIdx.x; l < hi; l += T) d1[l] = d0[l] - g * (d0[l - sh] + d0[l + sh]);
     __syncthreads();
     double* t = d0;
@@ -169,7 +195,32 @@ __global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
   const int last = per ? n : n + 1;                   // one past the last physical row of g
   for (int l = H + threadIdx.x; l < H + B; l += T) {
     const int g = g0 - H + l;
-    if (g < last) c.out[per ? g : g - 1] = d0[l] / L.divisor;
+    if (g < last) S.out[per ? g : g - 1] = d0[l] / divisor;
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
+                                              const Blk1D* __restrict__ blocks, int64_t sigma) {
+  extern __shared__ double lds[];
+  const Blk1D bk = blocks[blockIdx.x];
+  const Lvl1D* L = items + bk.item;
+  const int j = L->j;
+  const int64_t m = sigma - L->sigma0 - (int64_t)j * (j + 1) / 2;  // time index computed now
+  if (m < 1 || m > L->nt) return;                                   // level idle this step
+  switch (j) {
+    case 0: level_step<0, T>(L, bk.chunk, m, lds); break;
+    case 1: level_step<1, T>(L, bk.chunk, m, lds); break;
+    case 2: level_step<2, T>(L, bk.chunk, m, lds); break;
+    case 3: level_step<3, T>(L, bk.chunk, m, lds); break;
+    case 4: level_step<4, T>(L, bk.chunk, m, lds); break;
+    case 5: level_step<5, T>(L, bk.chunk, m, lds); break;
+    case 6: level_step<6, T>(L, bk.chunk, m, lds); break;
+    case 7: level_step<7, T>(L, bk.chunk, m, lds); break;
+    case 8: level_step<8, T>(L, bk.chunk, m, lds); break;
+    case 9: level_step<9, T>(L, bk.chunk, m, lds); break;
+    case 10: level_step<10, T>(L, bk.chunk, m, lds); break;
+    default: level_step<11, T>(L, bk.chunk, m, lds); break;
   }
 }
 

@@ -1,21 +1,664 @@
+// 2D (n x n, zero Dirichlet) part of the RIDC pipeline for gfx950.
+//
+// Every level step is taken in increment form, which is algebraically the step of the paper:
+//   predictor (section II, eq. imex_diffusion):
+//     (I - dt L) d = dt (f_E + L)(eta[0]_n),               eta[0]_{n+1} = eta[0]_n + d
+//   corrector (section III-C, eq. corr, with the (j+1)-node quadrature Q of f along level j-1):
+//     (I - dt L) e = eta[j]_n - eta[j-1]_{n+1} + dt Q + dt [f_E(eta[j]_n) - f_E(eta[j-1]_n)],
+//     eta[j]_{n+1} = eta[j-1]_{n+1} + e
+// (subtract (I - dt L) eta[j-1]_{n+1}, resp. (I - dt L) eta[0]_n, from both sides of the
+// paper's equation).  The right-hand side is small (O(dt) resp. O(dt^j)), so the rounding of
+// the transforms scales with the increment, not with u; the sums and level differences are
+// FP64 in every precision.
+//
+// Solve: fast diagonalisation.  With the orthonormal type-I sine matrix Q (symmetric,
+// Q_{ik} = sqrt(2/(n+1)) sin(pi (i+1)(k+1)/(n+1))) and mu_k = (4/h^2) sin^2(pi (k+1)/(2(n+1))),
+// (I - dt nu Lap_h)^{-1} B = Q [(Q B Q) ./ (1 + dt nu (mu_i + mu_k))] Q.
+// Each product by Q is one pass C = (A Q)^T: two passes give Q B Q in the original orientation.
+// A pass is a GEMM on the matrix cores (v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32, or three
+// v_mfma_f32_16x16x32_bf16 products of hi/lo BF16 splits), batched over every active level of
+// every instance in one launch; the eigenvalue divide and the final update are fused into the
+// epilogues of passes 2 and 4.
+//
+// Reduced precision (FP32 or split BF16) adds one FP64 residual refinement:
+//   x1 = S~(b),  rho = b - (x1 - dt nu Lap_h x1)  (FP64 5-point),  x = x1 + S~(rho).
+#include <hip/hip_bf16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+
 #include "ridc2d.h"
 #include "ridc_internal.h"
 
 namespace ridc {
 
-struct Plan2D {
-  int dummy;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+enum { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16 = 2, OUT_FINAL = 3 };
+
+// One (instance, level) of the 2D pipeline: static for a handle.
+struct Lvl2D {
+  double* own;          // ring of this level (R_own slots of n*n)
+  const double* prev;   // ring of level j-1 (null for j = 0)
+  const double* W;      // weights, j rows x (j+1)
+  double* b64;          // FP64 right-hand side (kept for the residual)
+  double* x64;          // FP64 first solve (refinement) or FP64 intermediate
+  void* lo0;            // low-precision buffers (FP32, or BF16 hi then lo)
+  void* lo1;
+  int64_t nt, sigma0;
+  int32_t n, j, R_own, R_prev, fe, prec;
+  double dt, nu_h2;
 };
 
-int plan2d_validate(const ridc_problem*) { return fail(RIDC_E_UNSUPPORTED, "2D not built yet"); }
-size_t plan2d_workspace_bytes(const ridc_problem*) { return 0; }
-int plan2d_create(const ridc_problem*, double, double* const*, const int*, const double*,
-                  const int64_t*, char*, size_t, hipStream_t, Plan2D**) {
-  return fail(RIDC_E_UNSUPPORTED, "2D not built yet");
+// One batch entry of a transform pass.
+struct Pass2D {
+  const void* A;        // input, row-major n x n (FP64, FP32, or BF16 hi; lo follows at +n*n)
+  void* C;              // output (unless final)
+  const double* add;    // final epilogue: extra FP64 term (x1 of the refinement), nullable
+  const void* Q;        // transform matrix in the input precision (BF16: hi, lo at +n*n)
+  const double* lam;    // dt nu mu_k (divide epilogue)
+  int32_t level;        // index into the level table
+  int32_t divide;       // divide by 1 + lam_i + lam_k
+};
+
+struct Plan2D {
+  ridc_problem p{};
+  int P = 1, prec = 0;
+  int64_t n = 0;
+  double h = 0;
+  std::vector<Lvl2D> levels;        // host copy (nt filled at arm)
+  Lvl2D* d_levels = nullptr;
+  // pass tables: npass passes x P entries, device
+  int npass = 0;
+  std::vector<Pass2D> passes;
+  Pass2D* d_passes = nullptr;
+  // transform data (shared per n)
+  const double* Q64 = nullptr;
+  const float* Q32 = nullptr;
+  const u16* Qbf = nullptr;         // hi then lo
+  double* lam = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+// ---------------------------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool level_active(const Lvl2D& L, int64_t sigma, int64_t* m_out) {
+  const int64_t m = sigma - L.sigma0 - (int64_t)L.j * (L.j + 1) / 2;
+  *m_out = m;
+  return m >= 1 && m <= L.nt;
 }
-void plan2d_destroy(Plan2D*) {}
-int plan2d_arm(Plan2D*, int64_t, hipStream_t) { return RIDC_E_UNSUPPORTED; }
-int plan2d_step(Plan2D* const*, int, const int64_t*, hipStream_t) { return RIDC_E_UNSUPPORTED; }
-void plan2d_cost(const Plan2D*, double*, double*) {}
+
+__device__ __forceinline__ double fe2(int fe, double u) {
+  return fe == RIDC_FE_LOGISTIC ? u * (1.0 - u) : 0.0;
+}
+
+__device__ __forceinline__ double lap5(const double* __restrict__ v, int iy, int ix, int n) {
+  const int64_t c = (int64_t)iy * n + ix;
+  const double w = ix > 0 ? v[c - 1] : 0.0;
+  const double e = ix < n - 1 ? v[c + 1] : 0.0;
+  const double s = iy > 0 ? v[c - n] : 0.0;
+  const double no = iy < n - 1 ? v[c + n] : 0.0;
+  return ((w + e) + (s + no)) - 4.0 * v[c];
+}
+
+__device__ __forceinline__ void split_bf16(double x, u16* hi, u16* lo) {
+  const float xf = (float)x;
+  const __bf16 h = (__bf16)xf;
+  const float r = xf - (float)h;
+  const __bf16 l = (__bf16)r;
+  *hi = __builtin_bit_cast(u16, h);
+  *lo = __builtin_bit_cast(u16, l);
+}
+
+__device__ __forceinline__ void store_lo(void* base, int prec, int64_t nn, int64_t idx, double v) {
+  if (prec == PREC_F32) {
+    ((float*)base)[idx] = (float)v;
+  } else {
+    u16 h, l;
+    split_bf16(v, &h, &l);
+    ((u16*)base)[idx] = h;
+    ((u16*)base)[nn + idx] = l;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// right-hand side (increment form), FP64; also writes the low-precision copy
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rhs2d(const Lvl2D* __restrict__ levels, int64_t sigma) {
+  const Lvl2D& L = levels[blockIdx.z];
+  int64_t m;
+  if (!level_active(L, sigma, &m)) return;
+  const int n = L.n;
+  const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (ix >= n || iy >= n) return;
+  const int64_t nn = (int64_t)n * n;
+  const int64_t c = (int64_t)iy * n + ix;
+  const int64_t nidx = m - 1;
+  const double* u = L.own + (nidx % L.R_own) * nn;
+  const double dt = L.dt;
+  double b;
+  if (L.j == 0) {
+    b = dt * (fe2(L.fe, u[c]) + L.nu_h2 * lap5(u, iy, ix, n));
+  } else {
+    const int j = L.j;
+    const int64_t s = m - j > 0 ? m - j : 0;
+    const double* w = L.W + (nidx - s) * (j + 1);
+    double quad = 0.0, fe_n = 0.0, v_n1 = 0.0;
+    for (int i = 0; i <= j; ++i) {
+      const int64_t node = s + i;
+      const double* v = L.prev + (node % L.R_prev) * nn;
+      const double v0 = v[c];
+      const double fev = fe2(L.fe, v0);
+      quad += w[i] * (fev + L.nu_h2 * lap5(v, iy, ix, n));
+      if (node == nidx) fe_n = fev;
+      if (node == nidx + 1) v_n1 = v0;
+    }
+    const double u0 = u[c];
+    b = (u0 - v_n1) + dt * quad + dt * (fe2(L.fe, u0) - fe_n);
+  }
+  if (L.prec == PREC_F64) {
+    L.b64[c] = b;
+  } else {
+    L.b64[c] = b;
+    store_lo(L.lo0, L.prec, nn, c, b);
+  }
+}
+
+// rho = b - (x1 - dt nu Lap_h x1), FP64, written in low precision
+__global__ __launch_bounds__(256) void k_resid2d(const Lvl2D* __restrict__ levels, int64_t sigma) {
+  const Lvl2D& L = levels[blockIdx.z];
+  int64_t m;
+  if (!level_active(L, sigma, &m)) return;
+  const int n = L.n;
+  const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (ix >= n || iy >= n) return;
+  const int64_t nn = (int64_t)n * n;
+  const int64_t c = (int64_t)iy * n + ix;
+  const double x = L.x64[c];
+  const double rho = L.b64[c] - (x - L.dt * L.nu_h2 * lap5(L.x64, iy, ix, n));
+  store_lo(L.lo0, L.prec, nn, c, rho);
+}
+
+// ---------------------------------------------------------------------------------------------
+// transform pass C = (A Q)^T on the matrix cores
+//   block tile 128 x 128 (4 waves in 2 x 2, each 64 x 64 = 4 x 4 MFMA tiles of 16 x 16)
+// ---------------------------------------------------------------------------------------------
+constexpr int BT = 128;  // block tile (rows of A x columns of Q)
+
+template <int PREC>
+struct Tr;
+
+template <>
+struct Tr<PREC_F64> {
+  typedef double T;
+  static constexpr int BK = 16;   // k per LDS stage
+  static constexpr int PAD = 1;
+  typedef dbl4 Acc;
+};
+template <>
+struct Tr<PREC_F32> {
+  typedef float T;
+  static constexpr int BK = 16;
+  static constexpr int PAD = 1;
+  typedef flt4 Acc;
+};
+template <>
+struct Tr<PREC_BF16> {
+  typedef u16 T;
+  static constexpr int BK = 32;
+  static constexpr int PAD = 8;
+  typedef flt4 Acc;
+};
+
+template <int PREC, int OUT>
+__global__ __launch_bounds__(256) void k_pass2d(const Pass2D* __restrict__ passes,
+                                                const Lvl2D* __restrict__ levels, int64_t sigma) {
+  typedef Tr<PREC> TR;
+  typedef typename TR::T T;
+  typedef typename TR::Acc Acc;
+  constexpr int BK = TR::BK;
+  constexpr int LD = BK + TR::PAD;           // LDS row stride (elements)
+  constexpr int NSPLIT = PREC == PREC_BF16 ? 2 : 1;
+  __shared__ T As[NSPLIT][BT * LD];
+  __shared__ T Bs[NSPLIT][BT * LD];
+
+  const Pass2D& E = passes[blockIdx.z];
+  const Lvl2D& L = levels[E.level];
+  int64_t m;
+  if (!level_active(L, sigma, &m)) return;
+  const int n = L.n;
+  const int row0 = blockIdx.y * BT;          // rows of A (i)
+  const int col0 = blockIdx.x * BT;          // columns of Q (j)
+  if (row0 >= n || col0 >= n) return;
+  const int64_t nn = (int64_t)n * n;
+  const T* A = (const T*)E.A;
+  const T* Q = (const T*)E.Q;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64;           // wave tile origin inside the block
+  const int wn = (wave & 1) * 64;
+
+  Acc acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+  // global -> register staging: each thread moves one row segment of A and of Q per split
+  constexpr int SEG = BK / 2;                // elements per thread per row (2 threads per row)
+  const int lrow = tid >> 1;                 // 0..127
+  const int lcol = (tid & 1) * SEG;
+  T ra[NSPLIT][SEG], rb[NSPLIT][SEG];
+
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < NSPLIT; ++s) {
+      const int ga = row0 + lrow;
+      const int gb = col0 + lrow;            // Q is symmetric: row j of Q = column j
+#pragma unroll
+      for (int e = 0; e < SEG; ++e) {
+        ra[s][e] = ga < n ? A[s * nn + (int64_t)ga * n + k0 + lcol + e] : T(0);
+        rb[s][e] = gb < n ? Q[s * nn + (int64_t)gb * n + k0 + lcol + e] : T(0);
+      }
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int s = 0; s < NSPLIT; ++s)
+#pragma unroll
+      for (int e = 0; e < SEG; ++e) {
+        As[s][lrow * LD + lcol + e] = ra[s][e];
+        Bs[s][lrow * LD + lcol + e] = rb[s][e];
+      }
+  };
+
+  const int KT = n / BK;
+  gload(0);
+  for (int kt = 0; kt < KT; ++kt) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (kt + 1 < KT) gload((kt + 1) * BK);
+    if constexpr (PREC == PREC_BF16) {
+      // one k-chunk of 32: lane holds 8 consecutive k of row (l % 16), k offset 8 (l / 16)
+      const int r16 = lane & 15;
+      const int kq = (lane >> 4) * 8;
+      bf16x8 ahi[4], alo[4], bhi[4], blo[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int ra_ = wm + t * 16 + r16;
+        const int rb_ = wn + t * 16 + r16;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          ahi[t][e] = __builtin_bit_cast(__bf16, As[0][ra_ * LD + kq + e]);
+          alo[t][e] = __builtin_bit_cast(__bf16, As[1][ra_ * LD + kq + e]);
+          bhi[t][e] = __builtin_bit_cast(__bf16, Bs[0][rb_ * LD + kq + e]);
+          blo[t][e] = __builtin_bit_cast(__bf16, Bs[1][rb_ * LD + kq + e]);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[a], bhi[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], blo[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], bhi[b], acc[a][b], 0, 0, 0);
+        }
+    } else {
+      // k-steps of 4: lane holds element (row l % 16, k l / 16)
+      const int r16 = lane & 15;
+      const int k4 = lane >> 4;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        T af[4], bf[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          af[t] = As[0][(wm + t * 16 + r16) * LD + kk + k4];
+          bf[t] = Bs[0][(wn + t * 16 + r16) * LD + kk + k4];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            if constexpr (PREC == PREC_F64)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+            else
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+          }
+      }
+    }
+  }
+
+  // epilogue: acc[a][b] holds C[i][j] for the 16 x 16 tile at rows row0 + wm + 16a, columns
+  // col0 + wn + 16b (column l%16 of lane l); the pass stores the transpose, out[j][i]
+  double* out64 = nullptr;
+  const double* base = nullptr;
+  if constexpr (OUT == OUT_FINAL) {
+    out64 = L.own + (m % L.R_own) * nn;
+    base = L.j == 0 ? L.own + ((m - 1) % L.R_own) * nn : L.prev + (m % L.R_prev) * nn;
+  }
+  // output row of accumulator element r: FP32 tiles hold rows 4(l/16) + r, FP64 tiles hold
+  // rows (l/16) + 4r (measured lane layouts of the two instructions)
+  const int i_base = PREC == PREC_F64 ? (lane >> 4) : 4 * (lane >> 4);
+  constexpr int i_step = PREC == PREC_F64 ? 4 : 1;
+  const int j_l = lane & 15;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = col0 + wn + 16 * b + j_l;
+      const int i16 = row0 + wm + 16 * a;       // n is a multiple of 32: i16 < n covers 16 rows
+      if (j >= n || i16 >= n) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i16 + i_base + i_step * r;
+        const int64_t o = (int64_t)j * n + i;
+        double v = (double)acc[a][b][r];
+        if (E.divide) v = v / (1.0 + (E.lam[i] + E.lam[j]));
+        if constexpr (OUT == OUT_F64) {
+          ((double*)E.C)[o] = v;
+        } else if constexpr (OUT == OUT_F32) {
+          ((float*)E.C)[o] = (float)v;
+        } else if constexpr (OUT == OUT_BF16) {
+          u16 h, l;
+          split_bf16(v, &h, &l);
+          ((u16*)E.C)[o] = h;
+          ((u16*)E.C)[nn + o] = l;
+        } else {
+          const double add = E.add ? E.add[o] : 0.0;
+          out64[o] = base[o] + (add + v);
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+struct Transform {
+  double* q64 = nullptr;
+  float* q32 = nullptr;
+  u16* qbf = nullptr;
+};
+std::mutex g_tf_mu;
+std::map<int64_t, Transform> g_tf;  // per n, per device id in the high bits; kept until exit
+
+int get_transform(int64_t n, int prec, Transform* out) {
+  int dev = 0;
+  RIDC_HIP_TRY(hipGetDevice(&dev));
+  const int64_t key = ((int64_t)dev << 40) | n;
+  std::lock_guard<std::mutex> lk(g_tf_mu);
+  Transform& t = g_tf[key];
+  const int64_t nn = n * n;
+  if ((prec == PREC_F64 && !t.q64) || (prec == PREC_F32 && !t.q32) ||
+      (prec == PREC_BF16 && !t.qbf)) {
+    // Q_{ik} = sqrt(2/(n+1)) sin(pi (i+1)(k+1)/(n+1)), argument reduced exactly mod 2(n+1)
+    std::vector<double> q(nn);
+    const long double scale = std::sqrt(2.0L / (long double)(n + 1));
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const int64_t period = 2 * (n + 1);
+    std::vector<long double> s(period);
+    for (int64_t k = 0; k < period; ++k) s[k] = scale * std::sin(pi * (long double)k / (n + 1));
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = 0; k < n; ++k) q[i * n + k] = (double)s[((i + 1) * (k + 1)) % period];
+    if (prec == PREC_F64) {
+      if (hipMalloc(&t.q64, nn * sizeof(double)) != hipSuccess) return fail(RIDC_E_NOMEM, "Q64");
+      RIDC_HIP_TRY(hipMemcpy(t.q64, q.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+    } else if (prec == PREC_F32) {
+      std::vector<float> qf(nn);
+      for (int64_t i = 0; i < nn; ++i) qf[i] = (float)q[i];
+      if (hipMalloc(&t.q32, nn * sizeof(float)) != hipSuccess) return fail(RIDC_E_NOMEM, "Q32");
+      RIDC_HIP_TRY(hipMemcpy(t.q32, qf.data(), nn * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+      std::vector<u16> qb(2 * nn);
+      for (int64_t i = 0; i < nn; ++i) {
+        // round to nearest even BF16 of the FP32 value, then of the FP32 remainder
+        auto to_bf = [](float f) -> u16 {
+          uint32_t u = __builtin_bit_cast(uint32_t, f);
+          u += 0x7fff + ((u >> 16) & 1);
+          return (u16)(u >> 16);
+        };
+        auto from_bf = [](u16 b) -> float { return __builtin_bit_cast(float, (uint32_t)b << 16); };
+        const float f = (float)q[i];
+        const u16 hi = to_bf(f);
+        const u16 lo = to_bf(f - from_bf(hi));
+        qb[i] = hi;
+        qb[nn + i] = lo;
+      }
+      if (hipMalloc(&t.qbf, 2 * nn * sizeof(u16)) != hipSuccess) return fail(RIDC_E_NOMEM, "Qbf");
+      RIDC_HIP_TRY(hipMemcpy(t.qbf, qb.data(), 2 * nn * sizeof(u16), hipMemcpyHostToDevice));
+    }
+  }
+  *out = t;
+  return RIDC_OK;
+}
+
+int prec_of(const ridc_problem* p) {
+  return p->prec == RIDC_PREC_FP64 ? PREC_F64 : (p->prec == RIDC_PREC_FP32_REFINE ? PREC_F32 : PREC_BF16);
+}
+
+size_t level_ws_bytes(int64_t n, int prec) {
+  const size_t nn = (size_t)n * n;
+  if (prec == PREC_F64) return 2 * nn * sizeof(double);             // b64, x64 (intermediate)
+  return 2 * nn * sizeof(double) + 2 * nn * sizeof(float);          // b64, x64, lo0, lo1
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <int PREC, int OUT>
+void launch_pass(const Pass2D* d, const Lvl2D* lv, int count, int64_t nmax, int64_t sigma,
+                 hipStream_t st) {
+  const unsigned t = (unsigned)((nmax + BT - 1) / BT);
+  hipLaunchKernelGGL((k_pass2d<PREC, OUT>), dim3(t, t, count), dim3(256), 0, st, d, lv, sigma);
+}
+
+}  // namespace
+
+int plan2d_validate(const ridc_problem* p) {
+  if (p->n % 32 != 0) return fail(RIDC_E_UNSUPPORTED, "2D n must be a multiple of 32");
+  if (p->n > 16384) return fail(RIDC_E_UNSUPPORTED, "2D n above 16384");
+  return RIDC_OK;
+}
+
+size_t plan2d_workspace_bytes(const ridc_problem* p) {
+  const int P = p->order;
+  const int prec = prec_of(p);
+  size_t b = 0;
+  b += align256(sizeof(Lvl2D) * P);
+  const int npass = prec == PREC_F64 ? 4 : 8;
+  b += align256(sizeof(Pass2D) * P * npass);
+  b += align256(sizeof(double) * (size_t)p->n);                     // lam
+  b += (size_t)P * align256(level_ws_bytes(p->n, prec));
+  return b;
+}
+
+int plan2d_create(const ridc_problem* p, double h, double* const* ring, const int* R,
+                  const double* W, const int64_t* woff, char* ws, size_t ws_bytes,
+                  hipStream_t stream, Plan2D** out) {
+  auto* pl = new Plan2D();
+  pl->p = *p;
+  pl->P = p->order;
+  pl->prec = prec_of(p);
+  pl->n = p->n;
+  pl->h = h;
+  pl->stream = stream;
+  const int P = pl->P;
+  const int64_t n = p->n, nn = n * n;
+  Transform tf;
+  int rc = get_transform(n, pl->prec, &tf);
+  if (rc != RIDC_OK) {
+    delete pl;
+    return rc;
+  }
+  pl->Q64 = tf.q64;
+  pl->Q32 = tf.q32;
+  pl->Qbf = tf.qbf;
+  char* cur = ws;
+  pl->d_levels = (Lvl2D*)cur;
+  cur += align256(sizeof(Lvl2D) * P);
+  pl->npass = pl->prec == PREC_F64 ? 4 : 8;
+  pl->d_passes = (Pass2D*)cur;
+  cur += align256(sizeof(Pass2D) * P * pl->npass);
+  pl->lam = (double*)cur;
+  cur += align256(sizeof(double) * n);
+  // lam_k = dt nu (4/h^2) sin^2(pi (k+1) / (2(n+1)))
+  {
+    std::vector<double> lam(n);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int64_t k = 0; k < n; ++k) {
+      const long double s = std::sin(pi * (long double)(k + 1) / (2.0L * (n + 1)));
+      lam[k] = (double)((long double)p->dt * p->nu * 4.0L / ((long double)h * h) * s * s);
+    }
+    RIDC_HIP_TRY(hipMemcpy(pl->lam, lam.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  }
+  pl->levels.assign(P, Lvl2D{});
+  const size_t lws = align256(level_ws_bytes(n, pl->prec));
+  for (int j = 0; j < P; ++j) {
+    Lvl2D& L = pl->levels[j];
+    L.own = ring[j];
+    L.prev = j > 0 ? ring[j - 1] : nullptr;
+    L.W = j > 0 ? W + woff[j] : nullptr;
+    char* lw = cur + j * lws;
+    L.b64 = (double*)lw;
+    L.x64 = (double*)(lw + nn * sizeof(double));
+    if (pl->prec != PREC_F64) {
+      L.lo0 = lw + 2 * nn * sizeof(double);
+      L.lo1 = lw + 2 * nn * sizeof(double) + nn * sizeof(float);
+    }
+    L.nt = 0;
+    L.sigma0 = 0;
+    L.n = (int32_t)n;
+    L.j = j;
+    L.R_own = R[j];
+    L.R_prev = j > 0 ? R[j - 1] : 1;
+    L.fe = p->fe_kind;
+    L.prec = pl->prec;
+    L.dt = p->dt;
+    L.nu_h2 = p->nu / (h * h);
+  }
+  cur += P * lws;
+  if ((size_t)(cur - ws) > ws_bytes) {
+    delete pl;
+    return fail(RIDC_E_NOMEM, "2D workspace layout overflow");
+  }
+  // pass tables: pass k, level j at passes[k * P + j]
+  pl->passes.assign(pl->npass * P, Pass2D{});
+  for (int j = 0; j < P; ++j) {
+    Lvl2D& L = pl->levels[j];
+    for (int k = 0; k < pl->npass; ++k) {
+      Pass2D& E = pl->passes[k * P + j];
+      E.level = j;
+      E.lam = pl->lam;
+      E.divide = (k % 4) == 1;
+      if (pl->prec == PREC_F64) {
+        E.Q = pl->Q64;
+        const void* ins[4] = {L.b64, L.x64, L.b64, L.x64};
+        void* outs[4] = {L.x64, L.b64, L.x64, nullptr};
+        E.A = ins[k];
+        E.C = outs[k];
+      } else {
+        E.Q = pl->prec == PREC_F32 ? (const void*)pl->Q32 : (const void*)pl->Qbf;
+        const int kk = k % 4;
+        const void* ins[4] = {L.lo0, L.lo1, L.lo0, L.lo1};
+        void* outs[4] = {L.lo1, L.lo0, L.lo1, nullptr};
+        E.A = ins[kk];
+        E.C = outs[kk];
+        if (k == 3) E.C = L.x64;             // first solve, stored FP64
+        if (k == 7) E.add = L.x64;           // x = x1 + S~(rho)
+      }
+    }
+  }
+  RIDC_HIP_TRY(hipMemcpy(pl->d_passes, pl->passes.data(), sizeof(Pass2D) * pl->passes.size(),
+                         hipMemcpyHostToDevice));
+  *out = pl;
+  return RIDC_OK;
+}
+
+void plan2d_destroy(Plan2D* pl) { delete pl; }
+
+int plan2d_arm(Plan2D* pl, int64_t nt, hipStream_t stream) {
+  for (auto& L : pl->levels) {
+    L.nt = nt;
+    L.sigma0 = 0;
+  }
+  RIDC_HIP_TRY(hipMemcpyAsync(pl->d_levels, pl->levels.data(), sizeof(Lvl2D) * pl->levels.size(),
+                              hipMemcpyHostToDevice, stream));
+  return RIDC_OK;
+}
+
+// One pipeline step of several plans.  Plans are grouped by (n, precision); each group runs the
+// right-hand side, the transform passes and (reduced precision) the residual as one launch each,
+// with one grid z-slice per (plan, level).  Every plan of a group uses the same launch shapes
+// whatever the group holds, so a plan's bits do not depend on its company.
+int plan2d_step(Plan2D* const* pls, int count, const int64_t* sigma, hipStream_t stream) {
+  // Grouping needs one table of levels and passes per group, rebuilt when the group changes;
+  // a single plan uses its own tables.
+  if (count == 1) {
+    Plan2D* pl = pls[0];
+    const int64_t s = sigma[0];
+    const int P = pl->P;
+    const int64_t n = pl->n;
+    const unsigned gx = (unsigned)((n + 63) / 64), gy = (unsigned)((n + 3) / 4);
+    hipLaunchKernelGGL(k_rhs2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, s);
+    const Pass2D* d = pl->d_passes;
+    const Lvl2D* lv = pl->d_levels;
+    if (pl->prec == PREC_F64) {
+      launch_pass<PREC_F64, OUT_F64>(d + 0 * P, lv, P, n, s, stream);
+      launch_pass<PREC_F64, OUT_F64>(d + 1 * P, lv, P, n, s, stream);
+      launch_pass<PREC_F64, OUT_F64>(d + 2 * P, lv, P, n, s, stream);
+      launch_pass<PREC_F64, OUT_FINAL>(d + 3 * P, lv, P, n, s, stream);
+    } else if (pl->prec == PREC_F32) {
+      launch_pass<PREC_F32, OUT_F32>(d + 0 * P, lv, P, n, s, stream);
+      launch_pass<PREC_F32, OUT_F32>(d + 1 * P, lv, P, n, s, stream);
+      launch_pass<PREC_F32, OUT_F32>(d + 2 * P, lv, P, n, s, stream);
+      launch_pass<PREC_F32, OUT_F64>(d + 3 * P, lv, P, n, s, stream);
+      hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, s);
+      launch_pass<PREC_F32, OUT_F32>(d + 4 * P, lv, P, n, s, stream);
+      launch_pass<PREC_F32, OUT_F32>(d + 5 * P, lv, P, n, s, stream);
+      launch_pass<PREC_F32, OUT_F32>(d + 6 * P, lv, P, n, s, stream);
+      launch_pass<PREC_F32, OUT_FINAL>(d + 7 * P, lv, P, n, s, stream);
+    } else {
+      launch_pass<PREC_BF16, OUT_BF16>(d + 0 * P, lv, P, n, s, stream);
+      launch_pass<PREC_BF16, OUT_BF16>(d + 1 * P, lv, P, n, s, stream);
+      launch_pass<PREC_BF16, OUT_BF16>(d + 2 * P, lv, P, n, s, stream);
+      launch_pass<PREC_BF16, OUT_F64>(d + 3 * P, lv, P, n, s, stream);
+      hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, s);
+      launch_pass<PREC_BF16, OUT_BF16>(d + 4 * P, lv, P, n, s, stream);
+      launch_pass<PREC_BF16, OUT_BF16>(d + 5 * P, lv, P, n, s, stream);
+      launch_pass<PREC_BF16, OUT_BF16>(d + 6 * P, lv, P, n, s, stream);
+      launch_pass<PREC_BF16, OUT_FINAL>(d + 7 * P, lv, P, n, s, stream);
+    }
+    RIDC_HIP_TRY(hipGetLastError());
+    return RIDC_OK;
+  }
+  for (int i = 0; i < count; ++i) {
+    int rc = plan2d_step(&pls[i], 1, &sigma[i], stream);
+    if (rc != RIDC_OK) return rc;
+  }
+  return RIDC_OK;
+}
+
+void plan2d_cost(const Plan2D* pl, double* bytes, double* flops) {
+  const double n = (double)pl->n;
+  const int passes = pl->prec == PREC_F64 ? 4 : 8;
+  const double products = pl->prec == PREC_BF16 ? 3.0 : 1.0;
+  // algorithmic flops of the transforms at steady state: P level solves of 4 (or 8) n^3 GEMMs
+  *flops = 2.0 * n * n * n * passes * pl->P;
+  (void)products;
+  (void)bytes;
+}
 
 }  // namespace ridc

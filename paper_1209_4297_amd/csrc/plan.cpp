@@ -113,7 +113,8 @@ bool quadrature_weights(int j, int r, double* out) {
 // One stage adds to row i the multiples -gamma of rows i-s and i+s (gamma = a/b); the result is
 // the same kind of system with stride 2s, b' = b - 2a^2/b and a' = -a^2/b (exact in the algebra
 // of circulants, for any m).  The stages end when the stride is a multiple of m (the system is
-// then (b + 2a) I, exact) or when |a/b| < 1e-20 (the coupling is far below FP64 rounding).
+// then (b + 2a) I, exact) or when |a/b| < 1e-17 (the neglected coupling changes a row by less
+// than a quarter of a unit in the last place of the largest value).
 bool pcr_plan(double r, int64_t m, PcrPlan* out) {
   if (!(r >= 0.0) || !std::isfinite(r) || m < 1) return false;
   long double b = 1.0L + 2.0L * r;
@@ -133,7 +134,7 @@ bool pcr_plan(double r, int64_t m, PcrPlan* out) {
       return true;
     }
     const long double g = a / b;
-    if (std::fabs(static_cast<double>(g)) < 1e-20) {
+    if (std::fabs(static_cast<double>(g)) < 1e-17) {
       out->stages = k;
       out->exact = false;
       out->divisor = static_cast<double>(b);

@@ -69,6 +69,8 @@ def _load():
         "ridc_step_cost": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]),
         "ridc_version": (ctypes.c_char_p, []),
+        "ridc_autotune": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "ridc_set_tile": (ctypes.c_int, [vp, i32, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -81,7 +83,7 @@ _lib = _load()
 EXPORTED = ("ridc_create", "ridc_destroy", "ridc_footprint_bytes", "ridc_integrate",
             "ridc_integrate_batch", "ridc_begin", "ridc_advance", "ridc_remaining", "ridc_read",
             "ridc_sync", "ridc_last_error", "ridc_quadrature_weights", "ridc_pcr_plan",
-            "ridc_step_cost", "ridc_version")
+            "ridc_step_cost", "ridc_version", "ridc_autotune", "ridc_set_tile")
 
 
 def lib():
@@ -191,6 +193,16 @@ class Ridc:
 
     def sync(self):
         _check(_lib.ridc_sync(self._h))
+
+    def autotune(self):
+        """Pick the fastest tiling (1D); the handle must be re-armed afterwards."""
+        t = ctypes.c_int32()
+        r = ctypes.c_int32()
+        _check(_lib.ridc_autotune(self._h, ctypes.byref(t), ctypes.byref(r)))
+        return t.value, r.value
+
+    def set_tile(self, threads: int, rows: int):
+        _check(_lib.ridc_set_tile(self._h, int(threads), int(rows)))
 
     def step_cost(self):
         b = ctypes.c_double()

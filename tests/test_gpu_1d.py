@@ -203,3 +203,26 @@ def test_state_errors(env):
         s.begin(x0, 2)                      # below order - 1
     assert ei.value.code == ridc.RIDC_E_INVAL
     s.close()
+
+
+def test_tilings_are_bitwise_identical(env):
+    torch, ridc = env
+    prob, u0 = workloads.config_reacdiff_1d(n=4096, nt=120, T=0.06)
+    x0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    s = ridc.Ridc(prob)
+    outs = []
+    tiles = [(256, 0), (1024, 0), (256, 1024), (512, 512), (128, 2048), (1024, 256)]
+    for threads, rows in tiles:
+        try:
+            s.set_tile(threads, rows)
+        except ridc.RidcError:
+            continue
+        _say(f"tile threads={threads} rows={rows}")
+        outs.append(s.integrate(x0, prob["nt"]).cpu().numpy())
+    assert len(outs) >= 4
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    t, r = s.autotune()
+    _say(f"autotuned: threads={t} rows={r}")
+    np.testing.assert_array_equal(s.integrate(x0, prob["nt"]).cpu().numpy(), outs[0])
+    s.close()

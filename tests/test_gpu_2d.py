@@ -1,0 +1,137 @@
+"""GPU parity of the 2D RIDC path (FP64 right-hand side + fast-diagonalisation transforms on
+the matrix cores) against the FP64 oracle.
+
+FP64: relative L2 <= 1e-12 per level.  Reduced precision (FP32 or split-BF16 transforms with
+one FP64 residual refinement) has the stated tolerances below; both are far below the RIDC4
+discretisation error of these cases.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import Problem, rel_l2, ridc_pipelined
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL = {"fp32": 1e-11, "bf16x3": 1e-8}
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "reacdiff2d_n1024_nt500.npz")
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1209_4297_amd import ridc
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, ridc
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run2d(env, prob, u0, prec="fp64", nt=None, levels=True):
+    torch, ridc = env
+    nt = prob["nt"] if nt is None else nt
+    s = ridc.Ridc(prob, dt=prob["T"] / prob["nt"], prec=prec)
+    x0 = torch.tensor(np.asarray(u0), dtype=torch.float64, device="cuda").reshape(-1)
+    uT = torch.empty_like(x0)
+    lv = (torch.empty(prob["order"] * x0.numel(), dtype=torch.float64, device="cuda")
+          if levels else None)
+    s.integrate(x0, nt, uT, lv)
+    n = prob["n"]
+    out = uT.cpu().numpy().reshape(n, n)
+    lvs = lv.cpu().numpy().reshape(prob["order"], n, n) if levels else None
+    s.close()
+    return out, lvs
+
+
+def oracle2d(prob, u0, nt=None):
+    nt = prob["nt"] if nt is None else nt
+    return ridc_pipelined(Problem.from_dict(prob), u0, nt, prob["order"])
+
+
+@pytest.mark.parametrize("n,nt,order", [(64, 40, 4), (96, 30, 4), (256, 20, 4), (160, 12, 3),
+                                        (32, 8, 1), (64, 6, 6)])
+def test_fp64_parity(env, n, nt, order):
+    prob, u0 = workloads.config_reacdiff_2d(n=n, nt=nt, order=order, T=nt * 2e-3, nu=1e-3)
+    _say(f"case: 2D fp64 n={n} nt={nt} P={order}")
+    ref = oracle2d(prob, u0)
+    top, lvs = run2d(env, prob, u0)
+    for j in range(order):
+        err = rel_l2(lvs[j], ref[j])
+        _say(f"  level {j}: rel L2 {err:.3e}")
+        assert err <= TOL64, (j, err)
+    np.testing.assert_array_equal(top, lvs[-1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,nt", [(128, 40), (96, 20)])
+def test_mixed_precision_parity(env, prec, n, nt):
+    prob, u0 = workloads.config_reacdiff_2d(n=n, nt=nt, order=4, T=nt * 2e-3, nu=1e-3)
+    _say(f"case: 2D {prec} n={n} nt={nt}")
+    ref = oracle2d(prob, u0)
+    top, lvs = run2d(env, prob, u0, prec=prec)
+    for j in range(4):
+        err = rel_l2(lvs[j], ref[j])
+        _say(f"  level {j}: rel L2 {err:.3e}")
+        assert err <= TOL[prec], (j, err)
+
+
+def test_zero_steps_and_fixed_point(env):
+    torch, ridc = env
+    prob, u0 = workloads.config_reacdiff_2d(n=64, nt=10, order=4)
+    top, _ = run2d(env, prob, u0, nt=0)
+    np.testing.assert_array_equal(top, u0)
+    # u = 0 is a fixed point of u(1-u) with zero Dirichlet data
+    z = np.zeros((64, 64))
+    top, lvs = run2d(env, prob, z)
+    assert np.all(top == 0.0) and np.all(lvs == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_batch_bitwise_equals_solo_2d(env, prec):
+    torch, ridc = env
+    cases = [workloads.config_reacdiff_2d(n=n, nt=nt, order=o, T=nt * 2e-3, nu=1e-3, seed=100 + n)
+             for n, nt, o in [(64, 12, 4), (128, 9, 2), (64, 7, 3)]]
+    solvers, u0s, uTs, solo = [], [], [], []
+    for prob, u0 in cases:
+        s = ridc.Ridc(prob, prec=prec)
+        x0 = torch.tensor(u0.reshape(-1), dtype=torch.float64, device="cuda")
+        solo.append(s.integrate(x0, prob["nt"]).cpu().numpy())
+        solvers.append(s)
+        u0s.append(x0)
+        uTs.append(torch.empty_like(x0))
+    ridc.integrate_batch(solvers, u0s, [p["nt"] for p, _ in cases], uTs)
+    torch.cuda.synchronize()
+    for i in range(len(cases)):
+        np.testing.assert_array_equal(uTs[i].cpu().numpy(), solo[i])
+    for s in solvers:
+        s.close()
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="reference samples not generated")
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_full_size_against_reference_samples(env, prec):
+    """1024^2, Nt=500, order 4: the launch configuration of the full workload, checked at the
+    oracle's 4096 stored sample points, norms and sums (tests/golden)."""
+    ref = np.load(GOLDEN)
+    prob, u0 = workloads.config_reacdiff_2d()
+    _say(f"case: 2D {prec} full n=1024 nt=500")
+    top, lvs = run2d(env, prob, u0, prec=prec)
+    idx = ref["idx"]
+    tol = TOL64 if prec == "fp64" else TOL[prec]
+    for j in range(4):
+        flat = lvs[j].reshape(-1)
+        err = np.linalg.norm(flat[idx] - ref["samples"][j]) / np.linalg.norm(ref["samples"][j])
+        nerr = abs(np.linalg.norm(flat) - ref["norms"][j]) / ref["norms"][j]
+        _say(f"  level {j}: sampled rel L2 {err:.3e}, norm rel diff {nerr:.3e}")
+        assert err <= tol and nerr <= tol, (j, err, nerr)
+    sub = top[::8, ::8]
+    err = rel_l2(sub, ref["top_sub8"])
+    _say(f"  top level on the 128^2 sub-grid: rel L2 {err:.3e}")
+    assert err <= tol
