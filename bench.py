@@ -1,14 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the RIDC hot path on one MI355X.
 
-Workload: 1D reaction-diffusion u_t = nu u_xx + u(1-u), Dirichlet 0 on [0,1], N = 8192 interior
-points, nu = 1e-3, eight seeded Gaussian bumps, RIDC order 4 (predictor + 3 correctors), T = 1,
-Nt = 2000 uniform steps, FP64.  One bench step is one whole integration (all Nt time steps of
-all four levels, i.e. Nt + 6 pipeline steps) with the data already resident in HBM.
+Default workload (``--workload reacdiff1d``): 1D reaction-diffusion u_t = nu u_xx + u(1-u),
+Dirichlet 0 on [0,1], N = 8192 interior points, nu = 1e-3, eight seeded Gaussian bumps, RIDC
+order 4 (predictor + 3 correctors), T = 1, Nt = 2000 uniform steps, FP64.  One bench step is
+one whole integration (all Nt time steps of all four levels, Nt + 6 pipeline steps) with the
+data already resident in HBM.  Other workloads: ``advdiff1d`` (N=128 periodic
+advection-diffusion), ``reacdiff2d`` (1024^2, Nt=500, ``--prec fp64|fp32|bf16x3``) and
+``batched1d`` (256 ragged periodic instances, Nt=1000, T=0.25, one grouped launch per step).
 
 Prints one JSON line: grid-point-steps/s (unknowns x Nt / wall time), the roofline of the
-dominant kernel (the fused 1D level-step) from per-launch HIP events, and the FP64 CPU oracle
-timed on the host on the same workload.
+dominant kernel (HIP events around back-to-back launches on the library's stream), and the FP64
+CPU oracle timed on the host on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -23,43 +26,244 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E datasheet peak
+HBM_PEAK_GBS = 8000.0                                    # MI355X HBM3E
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense matrix peaks
+METRIC = "RIDC4 grid-point-steps/s at matched L2 error vs FP64"
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="reacdiff1d",
+                    choices=["reacdiff1d", "advdiff1d", "reacdiff2d", "batched1d"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--profile-launches", type=int, default=400,
-                    help="steady-state launches timed one by one for the roofline")
+    ap.add_argument("--reps", type=int, default=200, help="launches timed for the roofline")
+    ap.add_argument("--tile", default=None,
+                    help="1D tiling 'threads,rows' instead of autotuning (rows 0 = whole cycle)")
     return ap.parse_args()
 
 
-def kernel_roofline(torch, ridc, solver, x0, nt, launches):
-    """Average duration of the fused level-step kernel, from HIP events around single launches.
+def oracle_time(fn):
+    """Run fn() with BLAS/FFT threads limited to one; returns (result, seconds)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # noqa: BLE001
+        limiter = None
+    t = time.perf_counter()
+    out = fn()
+    dt = time.perf_counter() - t
+    if limiter is not None:
+        limiter.unregister()
+    return out, dt
 
-    The launches are queued behind a sleep so that the host never starves the GPU; each one is
-    a steady-state pipeline step (all four levels active) on the solver's stream.
-    """
-    P = solver.order
-    first = P * (P - 1) // 2 + 1            # first step with every level active
-    solver.begin(x0, nt)
-    ridc.advance([solver], first - 1)
-    launches = min(launches, nt - first)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(launches)]
+
+def run_single(args, torch, ridc, prob, u0, prec, steps, warmup, tune=True):
+    """Whole integrations of one instance; returns (seconds per integration, result, solver)."""
+    s = ridc.Ridc(prob, prec=prec)
+    tile = None
+    if prob["dim"] == 1 and args.tile:
+        tile = tuple(int(x) for x in args.tile.split(","))
+        s.set_tile(*tile)
+    elif tune and prob["dim"] == 1:
+        tile = s.autotune()
+    x0 = torch.tensor(np.asarray(u0).reshape(-1), dtype=torch.float64, device="cuda")
+    uT = torch.empty_like(x0)
+    for _ in range(warmup):
+        s.integrate(x0, prob["nt"], uT, sync=False)
     torch.cuda.synchronize()
-    torch.cuda._sleep(int(2e8))             # let the host queue every launch first
-    stream = torch.cuda.current_stream()
-    for a, b in evs:
-        a.record(stream)
-        ridc.advance([solver], 1)
-        b.record(stream)
+    s.sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.integrate(x0, prob["nt"], uT, sync=False)
     torch.cuda.synchronize()
-    times_ms = np.array([a.elapsed_time(b) for a, b in evs])
-    return float(np.mean(times_ms)) * 1e-3, float(np.median(times_ms)) * 1e-3
+    el = (time.perf_counter() - t0) / steps
+    s.sync()
+    return el, uT.cpu().numpy(), s, x0, tile
+
+
+def roofline_single(ridc, s, x0, nt, reps, bound, prec):
+    P = s.order
+    s.begin(x0, nt)
+    ridc.advance([s], P * (P - 1) // 2)            # next step has every level active
+    us, work = s.kernel_time(reps)
+    s.sync()
+    if bound == "hbm":
+        ach = work / (us * 1e-6) / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_step1d",
+                "launch_us": round(us, 3), "bytes_per_launch": work}
+    peak = MFMA_PEAK_TFLOPS[prec]
+    ach = work / (us * 1e-6) / 1e12
+    return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(ach / peak, 5), "traffic": None,
+            "kernel": f"k_pass2d<{prec}>", "launch_us": round(us, 3), "flops_per_launch": work,
+            "note": ("algorithmic flops 2n^3 per level; the split-BF16 pass issues 3 BF16 "
+                     "products per output" if prec == "bf16x3" else
+                     "algorithmic flops 2n^3 per level")}
+
+
+def bench_1d(args, torch, ridc, which):
+    import workloads
+    if which == "reacdiff1d":
+        prob, u0 = workloads.config_reacdiff_1d()
+        desc = ("1D reaction-diffusion u_t = nu u_xx + u(1-u), Dirichlet [0,1], N=8192, "
+                "nu=1e-3, 8 seeded Gaussians, RIDC order 4, T=1, Nt=2000, FP64")
+        steps, warmup = args.steps or 20, args.warmup if args.warmup is not None else 3
+    else:
+        prob, u0 = workloads.config_advdiff_1d()
+        desc = ("1D advection-diffusion u_t + u_x = 0.1 u_xx, periodic [0,2pi), N=128, "
+                "u0=sin x, RIDC order 4, T=1, Nt=200, FP64")
+        steps, warmup = args.steps or 200, args.warmup if args.warmup is not None else 10
+    n, nt, P = prob["n"], prob["nt"], prob["order"]
+    el, out, s, x0, tile = run_single(args, torch, ridc, prob, u0, "fp64", steps, warmup)
+    roof = roofline_single(ridc, s, x0, nt, args.reps, "hbm", "fp64")
+    s.close()
+    cpu = rel = None
+    if not args.no_cpu:
+        from oracle import Problem, rel_l2, ridc_pipelined
+        reps = 1 if which == "reacdiff1d" else 20
+        ref, sec = oracle_time(lambda: [ridc_pipelined(Problem.from_dict(prob), u0, nt, P)[-1]
+                                        for _ in range(reps)][-1])
+        rel = rel_l2(out, ref)
+        cpu = {"value": round(n * nt * reps / sec, 1), "unit": "grid-point-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"the full workload {reps}x (N={n}, Nt={nt}, order {P}), {sec:.2f} s, "
+                         f"one thread; host has {os.cpu_count()} logical CPUs"}
+    return dict(value=n * nt / el, ms=1e3 * el, steps=steps, warmup=warmup, dtype="f64",
+                config={"workload": desc, "n": n, "nt": nt, "order": P,
+                        "pipeline_steps": nt + P * (P - 1) // 2,
+                        "tile": {"threads": tile[0], "rows": tile[1]}},
+                roofline=roof, cpu=cpu, check={"rel_l2_vs_oracle": rel})
+
+
+def bench_2d(args, torch, ridc):
+    import workloads
+    prob, u0 = workloads.config_reacdiff_2d()
+    n, nt, P = prob["n"], prob["nt"], prob["order"]
+    steps, warmup = args.steps or 3, args.warmup if args.warmup is not None else 1
+    el, out, s, x0, _ = run_single(args, torch, ridc, prob, u0, args.prec, steps, warmup)
+    roof = roofline_single(ridc, s, x0, nt, max(10, args.reps // 10), "mfma", args.prec)
+    s.close()
+    check = {}
+    golden = os.path.join(ROOT, "tests", "golden", "reacdiff2d_n1024_nt500.npz")
+    if os.path.exists(golden):
+        ref = np.load(golden)
+        flat = out.reshape(-1)
+        samp = ref["samples"][-1]
+        check["rel_l2_vs_oracle_samples"] = float(np.linalg.norm(flat[ref["idx"]] - samp)
+                                                  / np.linalg.norm(samp))
+        check["rel_l2_vs_oracle_subgrid"] = float(
+            np.linalg.norm(out.reshape(n, n)[::8, ::8] - ref["top_sub8"])
+            / np.linalg.norm(ref["top_sub8"]))
+    # discretisation error of RIDC4 at this Nt (Richardson with an FP64 run at 2 Nt)
+    prob2 = dict(prob, nt=2 * nt)
+    s2 = ridc.Ridc(prob2, prec="fp64")
+    u2 = s2.integrate(x0, 2 * nt).cpu().numpy()
+    s2.close()
+    err_disc = 16.0 / 15.0 * float(np.linalg.norm(out - u2) / np.linalg.norm(u2)) \
+        if args.prec == "fp64" else None
+    if args.prec != "fp64":
+        s3 = ridc.Ridc(prob, prec="fp64")
+        u64 = s3.integrate(x0, nt).cpu().numpy()
+        s3.close()
+        err_disc = 16.0 / 15.0 * float(np.linalg.norm(u64 - u2) / np.linalg.norm(u2))
+        mixed = float(np.linalg.norm(out - u64) / np.linalg.norm(u64))
+        check["rel_l2_vs_fp64_gpu"] = mixed
+        check["matched"] = bool(mixed <= 0.1 * err_disc)
+    check["err_disc_ridc4"] = err_disc
+    cpu = None
+    if not args.no_cpu:
+        from oracle import Problem, ridc_pipelined
+        nts = 6
+        _, sec = oracle_time(lambda: ridc_pipelined(Problem.from_dict(prob), u0, nts, P))
+        cpu = {"value": round(n * n * nts / sec, 1), "unit": "grid-point-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"the full 1024^2 grid for the first {nts} time steps of all {P} levels "
+                         f"({P * nts} level steps, {sec:.1f} s), one thread"}
+    desc = ("2D reaction-diffusion u_t = nu Lap u + u(1-u), Dirichlet [0,1]^2, 1024x1024, "
+            f"nu=1e-4, 8 seeded bumps, RIDC order 4, T=1, Nt=500, transforms {args.prec}")
+    return dict(value=n * n * nt / el, ms=1e3 * el, steps=steps, warmup=warmup,
+                dtype={"fp64": "f64", "fp32": "f32 transforms, f64 sums",
+                       "bf16x3": "bf16x3 transforms, f64 sums"}[args.prec],
+                config={"workload": desc, "n": n, "nt": nt, "order": P, "prec": args.prec,
+                        "pipeline_steps": nt + P * (P - 1) // 2},
+                roofline=roof, cpu=cpu, check=check)
+
+
+def bench_batched(args, torch, ridc):
+    import workloads
+    cases = workloads.config_batched_1d()
+    steps, warmup = args.steps or 3, args.warmup if args.warmup is not None else 1
+    solvers, u0s, uTs = [], [], []
+    for prob, u0 in cases:
+        s = ridc.Ridc(prob)
+        solvers.append(s)
+        u0s.append(torch.tensor(u0, dtype=torch.float64, device="cuda"))
+        uTs.append(torch.empty_like(u0s[-1]))
+    tuned = {}
+    for s in solvers:                                   # one measurement per distinct size
+        key = s.npts
+        if key not in tuned:
+            tuned[key] = s.autotune()
+        else:
+            s.set_tile(*tuned[key])
+    nts = [p["nt"] for p, _ in cases]
+    for _ in range(warmup):
+        ridc.integrate_batch(solvers, u0s, nts, uTs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ridc.integrate_batch(solvers, u0s, nts, uTs)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    total = sum(p["n"] for p, _ in cases) * cases[0][0]["nt"]
+    # roofline: one grouped launch of a steady-state step, events around single launches
+    for s, x0, nt in zip(solvers, u0s, nts):
+        s.begin(x0, nt)
+    ridc.advance(solvers, 6)
+    k = 50                                              # one table upload, then k launches
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    a.record(st)
+    ridc.advance(solvers, k)
+    b.record(st)
+    torch.cuda.synchronize()
+    us = a.elapsed_time(b) * 1e3 / k
+    bytes_per = sum(s.step_cost()[0] for s in solvers)
+    ach = bytes_per / (us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_step1d (grouped)",
+            "launch_us": round(us, 3), "bytes_per_launch": bytes_per}
+    outs = [u.cpu().numpy() for u in uTs]
+    for s in solvers:
+        s.close()
+    cpu = None
+    check = {}
+    if not args.no_cpu:
+        from oracle import Problem, rel_l2, ridc_pipelined
+        idx = [0, 1, 2, 3]
+        def run():
+            return [ridc_pipelined(Problem.from_dict(cases[i][0]), cases[i][1], nts[i], 4)[-1]
+                    for i in idx]
+        refs, sec = oracle_time(run)
+        check["rel_l2_vs_oracle_max_of_sample"] = max(rel_l2(outs[i], r) for i, r in zip(idx, refs))
+        pts = sum(cases[i][0]["n"] * nts[i] for i in idx)
+        cpu = {"value": round(pts / sec, 1), "unit": "grid-point-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"instances 0-3 of 256 (n = {[cases[i][0]['n'] for i in idx]}), full "
+                         f"Nt=1000, {sec:.1f} s, one thread"}
+    desc = ("256 periodic advection-diffusion instances, N ~ U{256..4096}, a ~ U(0.5,2), "
+            "nu ~ logU(1e-3,1e-1), 8 Fourier modes, RIDC order 4, Nt=1000, T=0.25, FP64")
+    return dict(value=total / el, ms=1e3 * el, steps=steps, warmup=warmup, dtype="f64",
+                config={"workload": desc, "instances": len(cases),
+                        "unknowns": sum(p["n"] for p, _ in cases), "nt": nts[0], "order": 4},
+                roofline=roof, cpu=cpu, check=check)
 
 
 def main():
@@ -70,87 +274,33 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
-    import workloads
     from paper_1209_4297_amd import ridc
-
-    prob, u0 = workloads.config_reacdiff_1d()
-    n, nt, P = prob["n"], prob["nt"], prob["order"]
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    solver = ridc.Ridc(prob)
-    tile = solver.autotune()                 # result-neutral tiling choice, measured
-    x0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
-    uT = torch.empty_like(x0)
-
-    for _ in range(args.warmup):
-        solver.integrate(x0, nt, uT, sync=False)
-    torch.cuda.synchronize()
-    solver.sync()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        solver.integrate(x0, nt, uT, sync=False)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    solver.sync()
-    gps = n * nt * args.steps / elapsed
-    ms_per_step = 1e3 * elapsed / args.steps
-    result = uT.cpu().numpy()
-
-    # roofline of the dominant kernel
-    bytes_per_launch, _ = solver.step_cost()
-    mean_s, median_s = kernel_roofline(torch, ridc, solver, x0, nt, args.profile_launches)
-    achieved = bytes_per_launch / mean_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": "k_step1d", "launch_us_mean": round(mean_s * 1e6, 3),
-                "launch_us_median": round(median_s * 1e6, 3),
-                "bytes_per_launch": bytes_per_launch}
-
-    cpu = None
-    rel = None
-    if not args.no_cpu:
-        from oracle import Problem, rel_l2, ridc_pipelined
-        try:
-            from threadpoolctl import threadpool_limits
-            limiter = threadpool_limits(limits=1)
-        except Exception:  # noqa: BLE001
-            limiter = None
-        p = Problem.from_dict(prob)
-        t1 = time.perf_counter()
-        ref = ridc_pipelined(p, u0, nt, P)[-1]
-        cpu_s = time.perf_counter() - t1
-        if limiter is not None:
-            limiter.unregister()
-        rel = rel_l2(result, ref)
-        cpu = {"value": round(n * nt / cpu_s, 1), "unit": "grid-point-steps/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"the full workload once (N={n}, Nt={nt}, order {P}), {cpu_s:.2f} s, "
-                         f"one thread; host has {os.cpu_count()} logical CPUs"}
-
+    if args.workload in ("reacdiff1d", "advdiff1d"):
+        r = bench_1d(args, torch, ridc, args.workload)
+    elif args.workload == "reacdiff2d":
+        r = bench_2d(args, torch, ridc)
+    else:
+        r = bench_batched(args, torch, ridc)
+    cfg = dict(r["config"], parallelism="single GPU")
     line = {
-        "metric": "RIDC4 grid-point-steps/s at matched L2 error vs FP64",
-        "value": round(gps, 1),
+        "metric": METRIC,
+        "value": round(r["value"], 1),
         "unit": "grid-point-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "steps": r["steps"],
+        "warmup": r["warmup"],
+        "ms_per_step": round(r["ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": r["dtype"],
         "data": "synthetic",
-        "config": {"workload": "1D reaction-diffusion u_t = nu u_xx + u(1-u), Dirichlet [0,1], "
-                               "N=8192, nu=1e-3, 8 seeded Gaussians, RIDC order 4, T=1, "
-                               "Nt=2000, FP64",
-                   "n": n, "nt": nt, "order": P, "pipeline_steps": nt + P * (P - 1) // 2,
-                   "tile": {"threads": tile[0], "rows": tile[1]},
-                   "parallelism": "single GPU"},
-        "rel_l2_vs_oracle": rel,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
+        "config": cfg,
+        "check": r["check"],
+        "roofline": r["roofline"],
+        "cpu_baseline": r["cpu"],
     }
-    solver.close()
     print(json.dumps(line), flush=True)
 
 

@@ -166,6 +166,15 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out);
  * shorter than the system).  Errors: RIDC_E_INVAL if the tiling does not fit.                 */
 int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows);
 
+/* Average duration of the dominant kernel, from HIP events on the handle's stream around `reps`
+ * back-to-back launches of the handle's next pipeline step (which must have every level
+ * active): the fused level step (1D) or the first transform pass over all levels (2D).  The
+ * launches recompute the same values (every launch reads inputs it does not write); the handle
+ * does not advance.  *work_per_launch (nullable) receives the algorithmic HBM bytes (1D) or
+ * flops (2D) of one launch.  Errors: RIDC_E_STATE if the next step is not a full one.        */
+int ridc_kernel_time(ridc_handle* h, int32_t reps, double* us_per_launch,
+                     double* work_per_launch);
+
 /* Library version string.                                                                     */
 const char* ridc_version(void);
 

@@ -797,6 +797,44 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out) {
   return RIDC_OK;
 }
 
+int ridc_kernel_time(ridc_handle* h, int32_t reps, double* us_per_launch, double* work_per_launch) {
+  if (!h || reps < 1 || !us_per_launch) return fail(RIDC_E_INVAL, "bad arguments");
+  if (h->nt < 0) return fail(RIDC_E_STATE, "handle not armed");
+  const int64_t s = h->sigma + 1;
+  const int64_t first_full = (int64_t)h->P * (h->P - 1) / 2 + 1;
+  if (s < first_full || s - first_full + 1 > h->nt)
+    return fail(RIDC_E_STATE, "the next pipeline step does not have every level active");
+  double bytes = 0, flops = 0;
+  int rc = ridc_step_cost(h, &bytes, &flops);
+  if (rc != RIDC_OK) return rc;
+  if (h->p.dim == 2) {
+    rc = plan2d_time_pass(h->p2, s, reps, h->stream, us_per_launch);
+    if (rc != RIDC_OK) return rc;
+    const int passes = h->p.prec == RIDC_PREC_FP64 ? 4 : 8;
+    if (work_per_launch) *work_per_launch = flops / passes;   // one pass over every level
+    return RIDC_OK;
+  }
+  hipEvent_t a, b;
+  RIDC_HIP_TRY(hipEventCreate(&a));
+  RIDC_HIP_TRY(hipEventCreate(&b));
+  rc = launch_solo_steps_1d(h, s, s);                           // warm
+  if (rc == RIDC_OK) {
+    (void)hipEventRecord(a, h->stream);
+    for (int r = 0; r < reps && rc == RIDC_OK; ++r) rc = launch_solo_steps_1d(h, s, s);
+    (void)hipEventRecord(b, h->stream);
+  }
+  float ms = 0;
+  hipError_t e = rc == RIDC_OK ? hipEventSynchronize(b) : hipSuccess;
+  if (rc == RIDC_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc != RIDC_OK) return rc;
+  if (e != hipSuccess) return fail(RIDC_E_HIP, std::string("kernel timing: ") + hipGetErrorString(e));
+  *us_per_launch = 1e3 * (double)ms / reps;
+  if (work_per_launch) *work_per_launch = bytes;
+  return RIDC_OK;
+}
+
 int ridc_step_cost(const ridc_handle* h, double* hbm_bytes, double* flops) {
   if (!h) return fail(RIDC_E_INVAL, "NULL handle");
   // steady state, all levels active: level 0 reads its value and writes one; level j >= 1 reads

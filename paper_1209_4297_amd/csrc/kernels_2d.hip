@@ -651,6 +651,37 @@ int plan2d_step(Plan2D* const* pls, int count, const int64_t* sigma, hipStream_t
   return RIDC_OK;
 }
 
+int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us) {
+  const int P = pl->P;
+  const int64_t n = pl->n;
+  const unsigned gx = (unsigned)((n + 63) / 64), gy = (unsigned)((n + 3) / 4);
+  // inputs of the first pass of this step, then `reps` back-to-back launches of that pass
+  hipLaunchKernelGGL(k_rhs2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, sigma);
+  hipEvent_t a, b;
+  RIDC_HIP_TRY(hipEventCreate(&a));
+  RIDC_HIP_TRY(hipEventCreate(&b));
+  auto one = [&]() {
+    if (pl->prec == PREC_F64)
+      launch_pass<PREC_F64, OUT_F64>(pl->d_passes, pl->d_levels, P, n, sigma, stream);
+    else if (pl->prec == PREC_F32)
+      launch_pass<PREC_F32, OUT_F32>(pl->d_passes, pl->d_levels, P, n, sigma, stream);
+    else
+      launch_pass<PREC_BF16, OUT_BF16>(pl->d_passes, pl->d_levels, P, n, sigma, stream);
+  };
+  one();
+  (void)hipEventRecord(a, stream);
+  for (int r = 0; r < reps; ++r) one();
+  (void)hipEventRecord(b, stream);
+  hipError_t e = hipEventSynchronize(b);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(RIDC_E_HIP, std::string("pass timing: ") + hipGetErrorString(e));
+  *us = 1e3 * (double)ms / reps;
+  return RIDC_OK;
+}
+
 void plan2d_cost(const Plan2D* pl, double* bytes, double* flops) {
   const double n = (double)pl->n;
   const int passes = pl->prec == PREC_F64 ? 4 : 8;

@@ -21,5 +21,8 @@ int plan2d_arm(Plan2D* pl, int64_t nt, hipStream_t stream);
 // One pipeline step of each plan; sigma[i] is plan i's own pipeline step.
 int plan2d_step(Plan2D* const* pls, int count, const int64_t* sigma, hipStream_t stream);
 void plan2d_cost(const Plan2D* pl, double* bytes, double* flops);
+// Average duration (us) of `reps` back-to-back launches of the first transform pass of step
+// `sigma` (every level active), after computing that step's right-hand side once.
+int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us);
 
 }  // namespace ridc

@@ -71,6 +71,8 @@ def _load():
         "ridc_version": (ctypes.c_char_p, []),
         "ridc_autotune": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "ridc_set_tile": (ctypes.c_int, [vp, i32, i32]),
+        "ridc_kernel_time": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -83,7 +85,8 @@ _lib = _load()
 EXPORTED = ("ridc_create", "ridc_destroy", "ridc_footprint_bytes", "ridc_integrate",
             "ridc_integrate_batch", "ridc_begin", "ridc_advance", "ridc_remaining", "ridc_read",
             "ridc_sync", "ridc_last_error", "ridc_quadrature_weights", "ridc_pcr_plan",
-            "ridc_step_cost", "ridc_version", "ridc_autotune", "ridc_set_tile")
+            "ridc_step_cost", "ridc_version", "ridc_autotune", "ridc_set_tile",
+            "ridc_kernel_time")
 
 
 def lib():
@@ -203,6 +206,14 @@ class Ridc:
 
     def set_tile(self, threads: int, rows: int):
         _check(_lib.ridc_set_tile(self._h, int(threads), int(rows)))
+
+    def kernel_time(self, reps: int = 50):
+        """(us per launch, algorithmic work per launch) of the dominant kernel at the next
+        pipeline step (bytes for 1D, flops for 2D)."""
+        us = ctypes.c_double()
+        w = ctypes.c_double()
+        _check(_lib.ridc_kernel_time(self._h, int(reps), ctypes.byref(us), ctypes.byref(w)))
+        return us.value, w.value
 
     def step_cost(self):
         b = ctypes.c_double()
