@@ -37,7 +37,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="reacdiff1d",
-                    choices=["reacdiff1d", "advdiff1d", "reacdiff2d", "batched1d"])
+                    choices=["reacdiff1d", "advdiff1d", "reacdiff2d", "batched1d", "serving"])
+    ap.add_argument("--horizon", type=float, default=10.0,
+                    help="serving: seconds of Poisson arrivals admitted")
+    ap.add_argument("--max-wall", type=float, default=40.0,
+                    help="serving: wall-clock cap; work still queued then is reported unserved")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--reps", type=int, default=200, help="launches timed for the roofline")
@@ -266,6 +270,54 @@ def bench_batched(args, torch, ridc):
                 roofline=roof, cpu=cpu, check=check)
 
 
+def bench_serving(args, torch, ridc):
+    """Poisson stream of 2D reaction-diffusion requests (200 req/s; side 128..1024, order 2..4,
+    Nt 100..500, split-BF16 or FP32 transforms with FP64 refinement), continuous batching."""
+    import workloads
+    from paper_1209_4297_amd.serve import GpuExecutor, Request, Server
+    arrivals = workloads.serving_requests(duration=args.horizon)
+    reqs = []
+    for i, a in enumerate(arrivals):
+        n = a["prob"]["n"]
+        u0 = workloads.bumps_2d(n, a["bump_seed"]).reshape(-1)
+        reqs.append(Request(rid=i, prob=a["prob"], u0=u0, nsteps=a["prob"]["nt"],
+                            prec=args.prec if args.prec != "fp64" else "bf16x3",
+                            t_arrival=a["t_arrival"]))
+    free, total = torch.cuda.mem_get_info()
+    srv = Server(GpuExecutor(), hbm_budget=int(min(free * 0.5, 64 * 2**30)), max_slots=96,
+                 tick_steps=8)
+    # warm the transform caches and kernels before the clock starts
+    for n in (128, 256, 512, 1024):
+        prob, u0 = workloads.config_reacdiff_2d(n=n, nt=3, order=4)
+        sv = ridc.Ridc(prob, prec=reqs[0].prec)
+        sv.integrate(torch.tensor(u0.reshape(-1), dtype=torch.float64, device="cuda"), 3)
+        sv.close()
+    torch.cuda.synchronize()
+    stats = srv.run(reqs, horizon=args.horizon, max_wall=args.max_wall)
+    # one finished request of each size checked against its solo integration (bitwise)
+    check = {"solo_bitwise_equal": True, "checked": 0}
+    seen = set()
+    for r in srv.done:
+        if r.status != "done" or r.prob["n"] in seen:
+            continue
+        seen.add(r.prob["n"])
+        sv = ridc.Ridc(r.prob, prec=r.prec)
+        alone = sv.integrate(torch.tensor(r.u0, dtype=torch.float64, device="cuda"), r.nsteps)
+        sv.close()
+        check["checked"] += 1
+        check["solo_bitwise_equal"] &= bool(torch.equal(alone, r.result))
+    desc = ("serving: Poisson 200 req/s 2D reaction-diffusion, side U{128,256,512,1024}, order "
+            "U{2,3,4}, nu logU(1e-5,1e-3), Nt U{100..500}, T=1, seeded bumps, transforms "
+            f"{reqs[0].prec} + FP64 refinement; arrivals for {args.horizon:.0f} s")
+    roof = None
+    return dict(value=stats["completed_grid_point_steps_per_s"], ms=1e3 * stats["wall_s"],
+                steps=1, warmup=0, dtype=f"{reqs[0].prec} transforms, f64 sums",
+                config={"workload": desc, "offered": len(reqs), **{k: stats[k] for k in (
+                    "completed", "status_counts", "p50_latency_s", "p99_latency_s",
+                    "completed_requests_per_s", "peak_resident", "peak_hbm_bytes", "ticks")}},
+                roofline=roof, cpu=None, check=check)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -276,10 +328,19 @@ def main():
     import torch
     from paper_1209_4297_amd import ridc
     torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        line = run_workload(args, torch, ridc)
+    print(json.dumps(line), flush=True)
+
+
+def run_workload(args, torch, ridc):
     if args.workload in ("reacdiff1d", "advdiff1d"):
         r = bench_1d(args, torch, ridc, args.workload)
     elif args.workload == "reacdiff2d":
         r = bench_2d(args, torch, ridc)
+    elif args.workload == "serving":
+        r = bench_serving(args, torch, ridc)
     else:
         r = bench_batched(args, torch, ridc)
     cfg = dict(r["config"], parallelism="single GPU")
@@ -301,7 +362,7 @@ def main():
         "roofline": r["roofline"],
         "cpu_baseline": r["cpu"],
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 if __name__ == "__main__":

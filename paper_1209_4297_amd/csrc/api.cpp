@@ -277,6 +277,7 @@ void build_items_1d(ridc_handle* h, const Tile1D& tile) {
   for (auto& it : h->proto) lds = std::max(lds, lds_bytes_1d(it));
   h->lds = lds;
   h->threads = tile.threads;
+  (void)prepare_1d_step(h->threads, h->lds);
 }
 
 // Grouped launch tables for ridc_advance over several 1D handles (one set per thread and
@@ -353,11 +354,8 @@ int launch_solo_steps_1d(ridc_handle* h, int64_t first, int64_t last) {
 int run_solo_steps(ridc_handle* h, int64_t first, int64_t last) {
   if (h->p.dim == 1) return launch_solo_steps_1d(h, first, last);
   Plan2D* pl = h->p2;
-  for (int64_t s = first; s <= last; ++s) {
-    int rc = plan2d_step(&pl, 1, &s, h->stream);
-    if (rc != RIDC_OK) return rc;
-  }
-  return RIDC_OK;
+  const int64_t before = first - 1;
+  return plan2d_advance(&pl, 1, &before, last - first + 1, h->stream);
 }
 
 int check_handles(ridc_handle* const* hs, int32_t count) {
@@ -602,24 +600,43 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
     size_t nitems = 0, nblocks = 0;
     for (auto* h : h1) {
       nitems += h->proto.size();
-      nblocks += h->blocks.size();
+      nblocks += std::max(h->blocks.size(), h->proto.size());
     }
     rc = arena_reserve(nitems, nblocks);
     if (rc != RIDC_OK) return rc;
+    // A batch keeps the GPU busy by itself, so every system uses its throughput tiling (the
+    // whole cycle in one workgroup when it fits: no halo recomputation), 256 threads, and the
+    // largest systems are dispatched first.  Tilings do not change results.
     size_t ii = 0, bi = 0, lds = 0;
-    int threads = 0;
+    const int threads = 256;
+    std::vector<std::pair<int64_t, Blk1D>> order;
     for (auto* h : h1) {
+      Tile1D wrap{1, 0, threads};
+      const bool use_wrap = tile_fits(&h->p, h->pcr, wrap);
       for (size_t j = 0; j < h->proto.size(); ++j) {
         Lvl1D it = h->proto[j];
         it.nt = h->nt;
         it.sigma0 = -h->sigma;  // the handle's own step = launch step + sigma
+        if (use_wrap) {
+          it.wrap = 1;
+          it.B = 0;
+          it.H = 0;
+          it.nchunks = 1;
+        }
         g_arena.h_items[ii + j] = it;
+        lds = std::max(lds, lds_bytes_1d(it));
+        const int nch = use_wrap ? 1 : it.nchunks;
+        for (int c = 0; c < nch; ++c)
+          order.push_back({(int64_t)h->p.n * (use_wrap ? 1 : 0) + (use_wrap ? 0 : it.B + 2 * it.H),
+                           Blk1D{(int32_t)(ii + j), c}});
       }
-      for (auto b : h->blocks) g_arena.h_blocks[bi++] = Blk1D{(int32_t)(ii + b.item), b.chunk};
       ii += h->proto.size();
-      lds = std::max(lds, h->lds);
-      threads = std::max(threads, h->threads);
     }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const auto& a, const auto& b) { return a.first > b.first; });
+    nblocks = order.size();
+    for (auto& o : order) g_arena.h_blocks[bi++] = o.second;
+    RIDC_HIP_TRY(prepare_1d_step(threads, lds));
     RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_items, g_arena.h_items, sizeof(Lvl1D) * nitems,
                                 hipMemcpyHostToDevice, stream));
     RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_blocks, g_arena.h_blocks, sizeof(Blk1D) * nblocks,
@@ -636,18 +653,15 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
   // ---- 2D handles: grouped per step by the 2D planner -----------------------------------------
   if (!h2.empty()) {
     std::vector<Plan2D*> plans;
-    std::vector<int64_t> sig;
+    std::vector<int64_t> before;
     int64_t steps2 = 0;
     for (auto* h : h2) {
       plans.push_back(h->p2);
+      before.push_back(h->sigma);
       steps2 = std::max(steps2, std::min(max_steps, h->total - h->sigma));
     }
-    for (int64_t s = 1; s <= steps2; ++s) {
-      sig.clear();
-      for (auto* h : h2) sig.push_back(h->sigma + s);
-      rc = plan2d_step(plans.data(), (int)plans.size(), sig.data(), stream);
-      if (rc != RIDC_OK) return rc;
-    }
+    rc = plan2d_advance(plans.data(), (int)plans.size(), before.data(), steps2, stream);
+    if (rc != RIDC_OK) return rc;
     for (auto* h : h2) h->sigma += std::min(max_steps, h->total - h->sigma);
   }
   return RIDC_OK;

@@ -256,19 +256,20 @@ hipError_t allow_lds(size_t lds_bytes) {
   return hipSuccess;
 }
 
+hipError_t prepare_1d_step(int threads, size_t lds_bytes) {
+  switch (threads) {
+    case 64: return allow_lds<64>(lds_bytes);
+    case 128: return allow_lds<128>(lds_bytes);
+    case 256: return allow_lds<256>(lds_bytes);
+    case 512: return allow_lds<512>(lds_bytes);
+    case 1024: return allow_lds<1024>(lds_bytes);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_1d_step(const Lvl1D* d_items, const Blk1D* d_blocks, int nblocks, int threads,
                           size_t lds_bytes, int64_t sigma, hipStream_t stream) {
   if (nblocks <= 0) return hipSuccess;
-  hipError_t e = hipSuccess;
-  switch (threads) {
-    case 64: e = allow_lds<64>(lds_bytes); break;
-    case 128: e = allow_lds<128>(lds_bytes); break;
-    case 256: e = allow_lds<256>(lds_bytes); break;
-    case 512: e = allow_lds<512>(lds_bytes); break;
-    case 1024: e = allow_lds<1024>(lds_bytes); break;
-    default: return hipErrorInvalidValue;
-  }
-  if (e != hipSuccess) return e;
   switch (threads) {
     case 64:
       hipLaunchKernelGGL(k_step1d<64>, dim3(nblocks), dim3(64), lds_bytes, stream, d_items,

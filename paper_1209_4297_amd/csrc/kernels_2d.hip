@@ -190,9 +190,11 @@ __global__ __launch_bounds__(256) void k_resid2d(const Lvl2D* __restrict__ level
 
 // ---------------------------------------------------------------------------------------------
 // transform pass C = (A Q)^T on the matrix cores
-//   block tile 128 x 128 (4 waves in 2 x 2, each 64 x 64 = 4 x 4 MFMA tiles of 16 x 16)
+//   block tile 128 x 128, 8 waves in 2 (rows) x 4 (columns), each wave 64 x 32 = 4 x 2 MFMA
+//   tiles of 16 x 16; k staged through LDS in slices of BK with 16-byte global loads
 // ---------------------------------------------------------------------------------------------
-constexpr int BT = 128;  // block tile (rows of A x columns of Q)
+constexpr int BT = 128;      // block tile (rows of A x columns of Q)
+constexpr int NTHR = 512;    // threads per block
 
 template <int PREC>
 struct Tr;
@@ -200,36 +202,38 @@ struct Tr;
 template <>
 struct Tr<PREC_F64> {
   typedef double T;
-  static constexpr int BK = 16;   // k per LDS stage
-  static constexpr int PAD = 1;
+  static constexpr int BK = 16;
   typedef dbl4 Acc;
 };
 template <>
 struct Tr<PREC_F32> {
   typedef float T;
-  static constexpr int BK = 16;
-  static constexpr int PAD = 1;
+  static constexpr int BK = 32;
   typedef flt4 Acc;
 };
 template <>
 struct Tr<PREC_BF16> {
   typedef u16 T;
   static constexpr int BK = 32;
-  static constexpr int PAD = 8;
   typedef flt4 Acc;
 };
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <int PREC, int OUT>
-__global__ __launch_bounds__(256) void k_pass2d(const Pass2D* __restrict__ passes,
-                                                const Lvl2D* __restrict__ levels, int64_t sigma) {
+__global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ passes,
+                                                 const Lvl2D* __restrict__ levels, int64_t sigma) {
   typedef Tr<PREC> TR;
   typedef typename TR::T T;
   typedef typename TR::Acc Acc;
   constexpr int BK = TR::BK;
-  constexpr int LD = BK + TR::PAD;           // LDS row stride (elements)
+  constexpr int ROWB = BK * (int)sizeof(T) + 16;     // LDS row stride in bytes (16-aligned)
+  constexpr int LDE = ROWB / (int)sizeof(T);          // ... in elements
+  constexpr int CH = BK * (int)sizeof(T) / 16;        // 16-byte chunks per row
   constexpr int NSPLIT = PREC == PREC_BF16 ? 2 : 1;
-  __shared__ T As[NSPLIT][BT * LD];
-  __shared__ T Bs[NSPLIT][BT * LD];
+  constexpr int CPT = BT * CH / NTHR;                 // chunks per thread per operand and split
+  __shared__ __attribute__((aligned(16))) T As[NSPLIT][BT * LDE];
+  __shared__ __attribute__((aligned(16))) T Bs[NSPLIT][BT * LDE];
 
   const Pass2D& E = passes[blockIdx.z];
   const Lvl2D& L = levels[E.level];
@@ -246,44 +250,43 @@ __global__ __launch_bounds__(256) void k_pass2d(const Pass2D* __restrict__ passe
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave >> 1) * 64;           // wave tile origin inside the block
-  const int wn = (wave & 1) * 64;
+  const int wm = (wave >> 2) * 64;           // wave tile origin inside the block
+  const int wn = (wave & 3) * 32;
 
-  Acc acc[4][4];
+  Acc acc[4][2];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+    for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-  // global -> register staging: each thread moves one row segment of A and of Q per split
-  constexpr int SEG = BK / 2;                // elements per thread per row (2 threads per row)
-  const int lrow = tid >> 1;                 // 0..127
-  const int lcol = (tid & 1) * SEG;
-  T ra[NSPLIT][SEG], rb[NSPLIT][SEG];
-
+  u32x4 ra[NSPLIT][CPT], rb[NSPLIT][CPT];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int s = 0; s < NSPLIT; ++s) {
-      const int ga = row0 + lrow;
-      const int gb = col0 + lrow;            // Q is symmetric: row j of Q = column j
+    for (int s = 0; s < NSPLIT; ++s)
 #pragma unroll
-      for (int e = 0; e < SEG; ++e) {
-        ra[s][e] = ga < n ? A[s * nn + (int64_t)ga * n + k0 + lcol + e] : T(0);
-        rb[s][e] = gb < n ? Q[s * nn + (int64_t)gb * n + k0 + lcol + e] : T(0);
+      for (int c = 0; c < CPT; ++c) {
+        const int id = tid + c * NTHR;
+        const int r = id / CH, q = id % CH;
+        const int ga = row0 + r, gb = col0 + r;         // Q symmetric: row j of Q = column j
+        const int64_t ko = k0 + q * (16 / (int)sizeof(T));
+        ra[s][c] = ga < n ? *(const u32x4*)(A + s * nn + (int64_t)ga * n + ko) : u32x4{0, 0, 0, 0};
+        rb[s][c] = gb < n ? *(const u32x4*)(Q + s * nn + (int64_t)gb * n + ko) : u32x4{0, 0, 0, 0};
       }
-    }
   };
   auto sstore = [&]() {
 #pragma unroll
     for (int s = 0; s < NSPLIT; ++s)
 #pragma unroll
-      for (int e = 0; e < SEG; ++e) {
-        As[s][lrow * LD + lcol + e] = ra[s][e];
-        Bs[s][lrow * LD + lcol + e] = rb[s][e];
+      for (int c = 0; c < CPT; ++c) {
+        const int id = tid + c * NTHR;
+        const int r = id / CH, q = id % CH;
+        *(u32x4*)((char*)As[s] + r * ROWB + q * 16) = ra[s][c];
+        *(u32x4*)((char*)Bs[s] + r * ROWB + q * 16) = rb[s][c];
       }
   };
 
   const int KT = n / BK;
+  const int r16 = lane & 15;
   gload(0);
   for (int kt = 0; kt < KT; ++kt) {
     __syncthreads();
@@ -291,46 +294,43 @@ __global__ __launch_bounds__(256) void k_pass2d(const Pass2D* __restrict__ passe
     __syncthreads();
     if (kt + 1 < KT) gload((kt + 1) * BK);
     if constexpr (PREC == PREC_BF16) {
-      // one k-chunk of 32: lane holds 8 consecutive k of row (l % 16), k offset 8 (l / 16)
-      const int r16 = lane & 15;
-      const int kq = (lane >> 4) * 8;
-      bf16x8 ahi[4], alo[4], bhi[4], blo[4];
+      // lane holds 8 consecutive k of row (l % 16), k offset 8 (l / 16)
+      const int kb = (lane >> 4) * 16;                 // byte offset of the 8 k values
+      bf16x8 ahi[4], alo[4], bhi[2], blo[2];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int ra_ = wm + t * 16 + r16;
-        const int rb_ = wn + t * 16 + r16;
+        const int ro = (wm + t * 16 + r16) * ROWB + kb;
+        ahi[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[0] + ro));
+        alo[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[1] + ro));
+      }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          ahi[t][e] = __builtin_bit_cast(__bf16, As[0][ra_ * LD + kq + e]);
-          alo[t][e] = __builtin_bit_cast(__bf16, As[1][ra_ * LD + kq + e]);
-          bhi[t][e] = __builtin_bit_cast(__bf16, Bs[0][rb_ * LD + kq + e]);
-          blo[t][e] = __builtin_bit_cast(__bf16, Bs[1][rb_ * LD + kq + e]);
-        }
+      for (int t = 0; t < 2; ++t) {
+        const int ro = (wn + t * 16 + r16) * ROWB + kb;
+        bhi[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)Bs[0] + ro));
+        blo[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)Bs[1] + ro));
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < 2; ++b) {
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[a], bhi[b], acc[a][b], 0, 0, 0);
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], blo[b], acc[a][b], 0, 0, 0);
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], bhi[b], acc[a][b], 0, 0, 0);
         }
     } else {
       // k-steps of 4: lane holds element (row l % 16, k l / 16)
-      const int r16 = lane & 15;
       const int k4 = lane >> 4;
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        T af[4], bf[4];
+        T af[4], bf[2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          af[t] = As[0][(wm + t * 16 + r16) * LD + kk + k4];
-          bf[t] = Bs[0][(wn + t * 16 + r16) * LD + kk + k4];
-        }
+        for (int t = 0; t < 4; ++t) af[t] = As[0][(wm + t * 16 + r16) * LDE + kk + k4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) bf[t] = Bs[0][(wn + t * 16 + r16) * LDE + kk + k4];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
+          for (int b = 0; b < 2; ++b) {
             if constexpr (PREC == PREC_F64)
               acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
             else
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void k_pass2d(const Pass2D* __restrict__ passe
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < 2; ++b) {
       const int j = col0 + wn + 16 * b + j_l;
       const int i16 = row0 + wm + 16 * a;       // n is a multiple of 32: i16 < n covers 16 rows
       if (j >= n || i16 >= n) continue;
@@ -462,7 +462,7 @@ template <int PREC, int OUT>
 void launch_pass(const Pass2D* d, const Lvl2D* lv, int count, int64_t nmax, int64_t sigma,
                  hipStream_t st) {
   const unsigned t = (unsigned)((nmax + BT - 1) / BT);
-  hipLaunchKernelGGL((k_pass2d<PREC, OUT>), dim3(t, t, count), dim3(256), 0, st, d, lv, sigma);
+  hipLaunchKernelGGL((k_pass2d<PREC, OUT>), dim3(t, t, count), dim3(NTHR), 0, st, d, lv, sigma);
 }
 
 }  // namespace
@@ -599,55 +599,166 @@ int plan2d_arm(Plan2D* pl, int64_t nt, hipStream_t stream) {
   return RIDC_OK;
 }
 
-// One pipeline step of several plans.  Plans are grouped by (n, precision); each group runs the
-// right-hand side, the transform passes and (reduced precision) the residual as one launch each,
-// with one grid z-slice per (plan, level).  Every plan of a group uses the same launch shapes
-// whatever the group holds, so a plan's bits do not depend on its company.
-int plan2d_step(Plan2D* const* pls, int count, const int64_t* sigma, hipStream_t stream) {
-  // Grouping needs one table of levels and passes per group, rebuilt when the group changes;
-  // a single plan uses its own tables.
+namespace {
+
+// Every stage of one pipeline step for `cnt` (plan, level) entries of one precision: the
+// right-hand side, the transform passes and (reduced precision) the residual, one launch each.
+// passes is pass-major: passes[k * cnt + e].
+void run_stages(int prec, const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nmax, int64_t s,
+                hipStream_t st) {
+  const unsigned gx = (unsigned)((nmax + 63) / 64), gy = (unsigned)((nmax + 3) / 4);
+  hipLaunchKernelGGL(k_rhs2d, dim3(gx, gy, cnt), dim3(256), 0, st, lv, s);
+  if (prec == PREC_F64) {
+    launch_pass<PREC_F64, OUT_F64>(d + 0 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F64, OUT_F64>(d + 1 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F64, OUT_F64>(d + 2 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F64, OUT_FINAL>(d + 3 * cnt, lv, cnt, nmax, s, st);
+  } else if (prec == PREC_F32) {
+    launch_pass<PREC_F32, OUT_F32>(d + 0 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F32, OUT_F64>(d + 3 * cnt, lv, cnt, nmax, s, st);
+    hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, cnt), dim3(256), 0, st, lv, s);
+    launch_pass<PREC_F32, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F32, OUT_FINAL>(d + 7 * cnt, lv, cnt, nmax, s, st);
+  } else {
+    launch_pass<PREC_BF16, OUT_BF16>(d + 0 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_BF16>(d + 1 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_BF16>(d + 2 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_F64>(d + 3 * cnt, lv, cnt, nmax, s, st);
+    hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, cnt), dim3(256), 0, st, lv, s);
+    launch_pass<PREC_BF16, OUT_BF16>(d + 4 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_BF16>(d + 5 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_BF16>(d + 6 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_FINAL>(d + 7 * cnt, lv, cnt, nmax, s, st);
+  }
+}
+
+// Launch tables of grouped plans (one set per calling thread and device; the pinned staging
+// copy is reused only after its previous upload completed).
+struct Arena2D {
+  int device = -1;
+  Lvl2D* d_lv = nullptr;
+  Pass2D* d_ps = nullptr;
+  Lvl2D* h_lv = nullptr;
+  Pass2D* h_ps = nullptr;
+  size_t cap_lv = 0, cap_ps = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+thread_local Arena2D g_a2;
+
+int arena2d_reserve(size_t nlv, size_t nps) {
+  int dev = 0;
+  RIDC_HIP_TRY(hipGetDevice(&dev));
+  if (g_a2.device != dev) {
+    g_a2 = Arena2D{};
+    g_a2.device = dev;
+  }
+  if (!g_a2.done) RIDC_HIP_TRY(hipEventCreateWithFlags(&g_a2.done, hipEventDisableTiming));
+  if (g_a2.pending) {
+    RIDC_HIP_TRY(hipEventSynchronize(g_a2.done));
+    g_a2.pending = false;
+  }
+  if (nlv > g_a2.cap_lv) {
+    if (g_a2.d_lv) (void)hipFree(g_a2.d_lv);
+    if (g_a2.h_lv) (void)hipHostFree(g_a2.h_lv);
+    g_a2.d_lv = nullptr;
+    g_a2.h_lv = nullptr;
+    const size_t cap = std::max(nlv, 2 * g_a2.cap_lv);
+    if (hipMalloc(&g_a2.d_lv, cap * sizeof(Lvl2D)) != hipSuccess) return fail(RIDC_E_NOMEM, "2D level table");
+    if (hipHostMalloc(&g_a2.h_lv, cap * sizeof(Lvl2D), hipHostMallocDefault) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "2D level staging");
+    g_a2.cap_lv = cap;
+  }
+  if (nps > g_a2.cap_ps) {
+    if (g_a2.d_ps) (void)hipFree(g_a2.d_ps);
+    if (g_a2.h_ps) (void)hipHostFree(g_a2.h_ps);
+    g_a2.d_ps = nullptr;
+    g_a2.h_ps = nullptr;
+    const size_t cap = std::max(nps, 2 * g_a2.cap_ps);
+    if (hipMalloc(&g_a2.d_ps, cap * sizeof(Pass2D)) != hipSuccess) return fail(RIDC_E_NOMEM, "2D pass table");
+    if (hipHostMalloc(&g_a2.h_ps, cap * sizeof(Pass2D), hipHostMallocDefault) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "2D pass staging");
+    g_a2.cap_ps = cap;
+  }
+  return RIDC_OK;
+}
+
+}  // namespace
+
+// Advance plans by `steps` pipeline steps.  A single plan uses its own tables.  Several plans
+// are grouped by (precision, n): each group runs every stage of a step as one launch with one
+// grid z-slice per (plan, level), with the same tile shapes as a single plan, so a plan's bits
+// do not depend on its company.  Plan i's own step during launch step s is sigma_before[i] + s.
+int plan2d_advance(Plan2D* const* pls, int count, const int64_t* sigma_before, int64_t steps,
+                   hipStream_t stream) {
+  if (count <= 0 || steps <= 0) return RIDC_OK;
   if (count == 1) {
     Plan2D* pl = pls[0];
-    const int64_t s = sigma[0];
-    const int P = pl->P;
-    const int64_t n = pl->n;
-    const unsigned gx = (unsigned)((n + 63) / 64), gy = (unsigned)((n + 3) / 4);
-    hipLaunchKernelGGL(k_rhs2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, s);
-    const Pass2D* d = pl->d_passes;
-    const Lvl2D* lv = pl->d_levels;
-    if (pl->prec == PREC_F64) {
-      launch_pass<PREC_F64, OUT_F64>(d + 0 * P, lv, P, n, s, stream);
-      launch_pass<PREC_F64, OUT_F64>(d + 1 * P, lv, P, n, s, stream);
-      launch_pass<PREC_F64, OUT_F64>(d + 2 * P, lv, P, n, s, stream);
-      launch_pass<PREC_F64, OUT_FINAL>(d + 3 * P, lv, P, n, s, stream);
-    } else if (pl->prec == PREC_F32) {
-      launch_pass<PREC_F32, OUT_F32>(d + 0 * P, lv, P, n, s, stream);
-      launch_pass<PREC_F32, OUT_F32>(d + 1 * P, lv, P, n, s, stream);
-      launch_pass<PREC_F32, OUT_F32>(d + 2 * P, lv, P, n, s, stream);
-      launch_pass<PREC_F32, OUT_F64>(d + 3 * P, lv, P, n, s, stream);
-      hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, s);
-      launch_pass<PREC_F32, OUT_F32>(d + 4 * P, lv, P, n, s, stream);
-      launch_pass<PREC_F32, OUT_F32>(d + 5 * P, lv, P, n, s, stream);
-      launch_pass<PREC_F32, OUT_F32>(d + 6 * P, lv, P, n, s, stream);
-      launch_pass<PREC_F32, OUT_FINAL>(d + 7 * P, lv, P, n, s, stream);
-    } else {
-      launch_pass<PREC_BF16, OUT_BF16>(d + 0 * P, lv, P, n, s, stream);
-      launch_pass<PREC_BF16, OUT_BF16>(d + 1 * P, lv, P, n, s, stream);
-      launch_pass<PREC_BF16, OUT_BF16>(d + 2 * P, lv, P, n, s, stream);
-      launch_pass<PREC_BF16, OUT_F64>(d + 3 * P, lv, P, n, s, stream);
-      hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, s);
-      launch_pass<PREC_BF16, OUT_BF16>(d + 4 * P, lv, P, n, s, stream);
-      launch_pass<PREC_BF16, OUT_BF16>(d + 5 * P, lv, P, n, s, stream);
-      launch_pass<PREC_BF16, OUT_BF16>(d + 6 * P, lv, P, n, s, stream);
-      launch_pass<PREC_BF16, OUT_FINAL>(d + 7 * P, lv, P, n, s, stream);
-    }
+    for (int64_t s = 1; s <= steps; ++s)
+      run_stages(pl->prec, pl->d_levels, pl->d_passes, pl->P, pl->n, sigma_before[0] + s, stream);
     RIDC_HIP_TRY(hipGetLastError());
     return RIDC_OK;
   }
+  // groups keyed by (prec, n), in first-seen order
+  std::vector<std::pair<std::pair<int, int64_t>, std::vector<int>>> groups;
+  size_t nlv = 0, nps = 0;
   for (int i = 0; i < count; ++i) {
-    int rc = plan2d_step(&pls[i], 1, &sigma[i], stream);
-    if (rc != RIDC_OK) return rc;
+    const auto key = std::make_pair(pls[i]->prec, pls[i]->n);
+    auto it = std::find_if(groups.begin(), groups.end(), [&](auto& g) { return g.first == key; });
+    if (it == groups.end()) {
+      groups.push_back({key, {}});
+      it = groups.end() - 1;
+    }
+    it->second.push_back(i);
+    nlv += pls[i]->P;
+    nps += (size_t)pls[i]->P * pls[i]->npass;
   }
+  int rc = arena2d_reserve(nlv, nps);
+  if (rc != RIDC_OK) return rc;
+  struct G {
+    int prec, cnt;
+    int64_t n;
+    size_t lv_off, ps_off;
+  };
+  std::vector<G> gs;
+  size_t lo = 0, po = 0;
+  for (auto& g : groups) {
+    const int prec = g.first.first;
+    const int npass = prec == PREC_F64 ? 4 : 8;
+    int cnt = 0;
+    for (int i : g.second) cnt += pls[i]->P;
+    G gg{prec, cnt, g.first.second, lo, po};
+    int e = 0;
+    for (int i : g.second) {
+      Plan2D* pl = pls[i];
+      for (int j = 0; j < pl->P; ++j) {
+        Lvl2D L = pl->levels[j];
+        L.sigma0 = -sigma_before[i];
+        g_a2.h_lv[lo + e + j] = L;
+        for (int k = 0; k < npass; ++k) {
+          Pass2D E = pl->passes[k * pl->P + j];
+          E.level = e + j;
+          g_a2.h_ps[po + (size_t)k * cnt + e + j] = E;
+        }
+      }
+      e += pl->P;
+    }
+    lo += cnt;
+    po += (size_t)cnt * npass;
+    gs.push_back(gg);
+  }
+  RIDC_HIP_TRY(hipMemcpyAsync(g_a2.d_lv, g_a2.h_lv, lo * sizeof(Lvl2D), hipMemcpyHostToDevice, stream));
+  RIDC_HIP_TRY(hipMemcpyAsync(g_a2.d_ps, g_a2.h_ps, po * sizeof(Pass2D), hipMemcpyHostToDevice, stream));
+  RIDC_HIP_TRY(hipEventRecord(g_a2.done, stream));
+  g_a2.pending = true;
+  for (int64_t s = 1; s <= steps; ++s)
+    for (auto& g : gs)
+      run_stages(g.prec, g_a2.d_lv + g.lv_off, g_a2.d_ps + g.ps_off, g.cnt, g.n, s, stream);
+  RIDC_HIP_TRY(hipGetLastError());
   return RIDC_OK;
 }
 

@@ -18,8 +18,10 @@ int plan2d_create(const ridc_problem* p, double h, double* const* ring, const in
                   hipStream_t stream, Plan2D** out);
 void plan2d_destroy(Plan2D* pl);
 int plan2d_arm(Plan2D* pl, int64_t nt, hipStream_t stream);
-// One pipeline step of each plan; sigma[i] is plan i's own pipeline step.
-int plan2d_step(Plan2D* const* pls, int count, const int64_t* sigma, hipStream_t stream);
+// Advance plans by `steps` pipeline steps; plan i's own step during launch step s is
+// sigma_before[i] + s.  Plans sharing (precision, n) share every launch.
+int plan2d_advance(Plan2D* const* pls, int count, const int64_t* sigma_before, int64_t steps,
+                   hipStream_t stream);
 void plan2d_cost(const Plan2D* pl, double* bytes, double* flops);
 // Average duration (us) of `reps` back-to-back launches of the first transform pass of step
 // `sigma` (every level active), after computing that step's right-hand side once.

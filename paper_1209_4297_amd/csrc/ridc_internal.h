@@ -81,6 +81,10 @@ struct Blk1D {
   int32_t chunk;
 };
 
+// Allow `lds_bytes` of dynamic LDS for the level-step kernel with `threads` threads (host call,
+// made when a tiling is chosen, never inside graph capture).
+hipError_t prepare_1d_step(int threads, size_t lds_bytes);
+
 // Launch one pipeline step of a grouped 1D batch.
 hipError_t launch_1d_step(const Lvl1D* d_items, const Blk1D* d_blocks, int nblocks, int threads,
                           size_t lds_bytes, int64_t sigma, hipStream_t stream);
