@@ -45,8 +45,13 @@ def parse():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--reps", type=int, default=200, help="launches timed for the roofline")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy a float64 tensor of this many MiB three times (a plain "
+                         "copy kernel of known size, to scale hardware byte counters)")
+    ap.add_argument("--nt", type=int, default=None,
+                    help="override the number of time steps (short runs for counter profiling)")
     ap.add_argument("--tile", default=None,
-                    help="1D tiling 'threads,rows' instead of autotuning (rows 0 = whole cycle)")
+                    help="1D tiling 'threads,rows,flags' instead of autotuning (rows 0 = whole cycle)")
     return ap.parse_args()
 
 
@@ -70,7 +75,8 @@ def run_single(args, torch, ridc, prob, u0, prec, steps, warmup, tune=True):
     s = ridc.Ridc(prob, prec=prec)
     tile = None
     if prob["dim"] == 1 and args.tile:
-        tile = tuple(int(x) for x in args.tile.split(","))
+        tile = tuple(int(x) for x in args.tile.split(",")) + (0,)
+        tile = tile[:3]
         s.set_tile(*tile)
     elif tune and prob["dim"] == 1:
         tile = s.autotune()
@@ -114,6 +120,8 @@ def bench_1d(args, torch, ridc, which):
     import workloads
     if which == "reacdiff1d":
         prob, u0 = workloads.config_reacdiff_1d()
+        if args.nt:
+            prob = dict(prob, nt=args.nt, T=prob["T"] * args.nt / prob["nt"])
         desc = ("1D reaction-diffusion u_t = nu u_xx + u(1-u), Dirichlet [0,1], N=8192, "
                 "nu=1e-3, 8 seeded Gaussians, RIDC order 4, T=1, Nt=2000, FP64")
         steps, warmup = args.steps or 20, args.warmup if args.warmup is not None else 3
@@ -140,7 +148,7 @@ def bench_1d(args, torch, ridc, which):
     return dict(value=n * nt / el, ms=1e3 * el, steps=steps, warmup=warmup, dtype="f64",
                 config={"workload": desc, "n": n, "nt": nt, "order": P,
                         "pipeline_steps": nt + P * (P - 1) // 2,
-                        "tile": {"threads": tile[0], "rows": tile[1]}},
+                        "tile": {"threads": tile[0], "rows": tile[1], "flags": tile[2]}},
                 roofline=roof, cpu=cpu, check={"rel_l2_vs_oracle": rel})
 
 
@@ -330,6 +338,13 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
+        if args.calibrate_copy:
+            src = torch.ones(args.calibrate_copy * 2**17, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
         line = run_workload(args, torch, ridc)
     print(json.dumps(line), flush=True)
 

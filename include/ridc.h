@@ -158,13 +158,15 @@ int ridc_step_cost(const ridc_handle* h, double* hbm_bytes, double* flops);
  * for later handles with the same (n, boundary, PCR stages).  Every tiling performs the same
  * operations for every output value, so results are bitwise independent of the choice.  The
  * tuning steps overwrite the level rings: the handle must be re-armed (ridc_begin) afterwards.
- * threads_out/rows_out (nullable) receive the choice (rows 0 = whole cycle).  2D: no-op.     */
-int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out);
+ * threads_out/rows_out/flags_out (nullable) receive the choice (rows 0 = whole cycle; flags as
+ * in ridc_set_tile).  2D: no-op.                                                              */
+int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out);
 
 /* Force a 1D tiling: threads in {64,128,256,512,1024}; rows = 0 for the whole cycle in one
  * workgroup, else chunks of `rows` rows (allowed when the PCR coupling vanishes within a halo
- * shorter than the system).  Errors: RIDC_E_INVAL if the tiling does not fit.                 */
-int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows);
+ * shorter than the system); flags bit 0 = write level values with nontemporal stores.
+ * Errors: RIDC_E_INVAL if the tiling does not fit.                                            */
+int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags);
 
 /* Average duration of the dominant kernel, from HIP events on the handle's stream around `reps`
  * back-to-back launches of the handle's next pipeline step (which must have every level

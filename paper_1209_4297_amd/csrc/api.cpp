@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 
@@ -59,6 +60,8 @@ struct ridc_handle {
   std::vector<Blk1D> blocks;  // blocks of a solo launch
   Lvl1D* d_items = nullptr;   // device copies (inside the pool)
   Blk1D* d_blocks = nullptr;
+  Solo1D solo{};              // kernel-argument descriptor of a single-instance launch
+  int solo_blocks = 0;
   size_t blocks_cap = 0;
   size_t lds = 0;
 
@@ -133,6 +136,7 @@ struct Tile1D {
   int wrap = 1;
   int B = 0;
   int threads = 256;
+  int nt_store = 0;   // write new level values with nontemporal stores
 };
 
 std::mutex g_tune_mu;
@@ -278,6 +282,31 @@ void build_items_1d(ridc_handle* h, const Tile1D& tile) {
   h->lds = lds;
   h->threads = tile.threads;
   (void)prepare_1d_step(h->threads, h->lds);
+  Solo1D& a = h->solo;
+  a = Solo1D{};
+  for (int j = 0; j < P; ++j) {
+    a.ring[j] = h->ring[j];
+    a.W[j] = j > 0 ? h->W + h->woff[j] : nullptr;
+    a.R[j] = h->R[j];
+  }
+  a.gamma = (const double*)((const char*)h->d_items + offsetof(Lvl1D, gamma));
+  a.shift = (const int32_t*)((const char*)h->d_items + offsetof(Lvl1D, shift));
+  a.nt = h->nt < 0 ? 0 : h->nt;
+  a.nchunks = nchunks;
+  a.n = (int32_t)p.n;
+  a.M = (int32_t)M;
+  a.bc = p.bc;
+  a.fe = p.fe_kind;
+  a.stages = h->pcr.stages;
+  a.wrap = tile.wrap;
+  a.B = tile.wrap ? 0 : tile.B;
+  a.H = H;
+  a.nt_store = tile.nt_store;
+  a.dt = p.dt;
+  a.a_2h = p.a / (2.0 * h->h);
+  a.nu_h2 = p.nu / (h->h * h->h);
+  a.divisor = h->pcr.divisor;
+  h->solo_blocks = P * nchunks;
 }
 
 // Grouped launch tables for ridc_advance over several 1D handles (one set per thread and
@@ -338,6 +367,7 @@ int arena_reserve(size_t nitems, size_t nblocks) {
 int64_t pipeline_steps(int64_t nt, int P) { return nt > 0 ? nt + (int64_t)P * (P - 1) / 2 : 0; }
 
 int upload_solo_items(ridc_handle* h) {
+  h->solo.nt = h->nt;
   for (auto& it : h->proto) it.nt = h->nt;
   RIDC_HIP_TRY(hipMemcpyAsync(h->d_items, h->proto.data(), sizeof(Lvl1D) * h->proto.size(),
                               hipMemcpyHostToDevice, h->stream));
@@ -346,8 +376,7 @@ int upload_solo_items(ridc_handle* h) {
 
 int launch_solo_steps_1d(ridc_handle* h, int64_t first, int64_t last) {
   for (int64_t s = first; s <= last; ++s)
-    RIDC_HIP_TRY(launch_1d_step(h->d_items, h->d_blocks, (int)h->blocks.size(), h->threads,
-                                h->lds, s, h->stream));
+    RIDC_HIP_TRY(launch_1d_solo(h->solo, h->solo_blocks, h->threads, h->lds, s, h->stream));
   return RIDC_OK;
 }
 
@@ -373,6 +402,7 @@ int apply_tile_1d(ridc_handle* h, const Tile1D& t) {
   const size_t nchunks = t.wrap ? 1 : (size_t)((h->p.n + t.B - 1) / t.B);
   if (nchunks * h->P > h->blocks_cap) return fail(RIDC_E_INVAL, "tile finer than the minimum chunk");
   build_items_1d(h, t);
+  h->solo.nt = h->nt < 0 ? 0 : h->nt;
   RIDC_HIP_TRY(hipMemcpyAsync(h->d_blocks, h->blocks.data(), sizeof(Blk1D) * h->blocks.size(),
                               hipMemcpyHostToDevice, h->stream));
   for (auto& it : h->proto) it.nt = h->nt < 0 ? 0 : h->nt;
@@ -392,6 +422,7 @@ int time_tile_1d(ridc_handle* h, const Tile1D& t, int reps, float* ms) {
   int rc = apply_tile_1d(h, t);
   if (rc != RIDC_OK) return rc;
   for (auto& it : h->proto) it.nt = (int64_t)1 << 40;
+  h->solo.nt = (int64_t)1 << 40;
   RIDC_HIP_TRY(hipMemcpyAsync(h->d_items, h->proto.data(), sizeof(Lvl1D) * h->proto.size(),
                               hipMemcpyHostToDevice, h->stream));
   hipEvent_t a, b;
@@ -754,18 +785,20 @@ int ridc_integrate_batch(ridc_handle* const* hs, int32_t count, const double* co
   return RIDC_OK;
 }
 
-int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows) {
+int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags) {
   if (!h) return fail(RIDC_E_INVAL, "NULL handle");
   if (h->p.dim != 1) return fail(RIDC_E_UNSUPPORTED, "tiles are chosen per system in 1D only");
-  Tile1D t{rows == 0 ? 1 : 0, rows, threads};
+  if (rows < 0 || (flags & ~1)) return fail(RIDC_E_INVAL, "bad rows or flags");
+  Tile1D t{rows == 0 ? 1 : 0, rows, threads, flags & 1};
   return apply_tile_1d(h, t);
 }
 
-int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out) {
+int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out) {
   if (!h) return fail(RIDC_E_INVAL, "NULL handle");
   if (h->p.dim != 1) {
-    if (threads_out) *threads_out = 256;
+    if (threads_out) *threads_out = 512;
     if (rows_out) *rows_out = 128;
+    if (flags_out) *flags_out = 0;
     return RIDC_OK;                      // 2D launch shapes are fixed per precision
   }
   const size_t ring_bytes = 0;
@@ -775,10 +808,11 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out) {
   for (int j = 0; j < h->P; ++j) slots += h->R[j];
   RIDC_HIP_TRY(hipMemsetAsync(h->ring[0], 0, sizeof(double) * (size_t)(slots * h->npts), h->stream));
   std::vector<Tile1D> cands;
-  for (int T : {256, 512, 1024}) {
-    cands.push_back(Tile1D{1, 0, T});
-    for (int B : {kMinChunk, 256, 512, 1024, 2048, 4096}) cands.push_back(Tile1D{0, B, T});
-  }
+  for (int nts : {0, 1})
+    for (int T : {256, 512, 1024}) {
+      cands.push_back(Tile1D{1, 0, T, nts});
+      for (int B : {kMinChunk, 256, 512, 1024, 2048, 4096}) cands.push_back(Tile1D{0, B, T, nts});
+    }
   Tile1D best{};
   float best_ms = 1e30f;
   for (const Tile1D& t : cands) {
@@ -808,6 +842,7 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out) {
   if (rc != RIDC_OK) return rc;
   if (threads_out) *threads_out = best.threads;
   if (rows_out) *rows_out = best.wrap ? 0 : best.B;
+  if (flags_out) *flags_out = best.nt_store;
   return RIDC_OK;
 }
 

@@ -94,10 +94,28 @@ __device__ __forceinline__ double rhs_ext(const Geo& G, const Step<J>& S, int g)
   return -rhs_row<J>(G, S, G.M - g - 1);
 }
 
+// Everything one level step reads besides the rings: built from a descriptor table entry
+// (batched launches) or from the kernel arguments (a single instance's launch).
+struct View {
+  double* own;
+  const double* prev;
+  const double* W;
+  const double* gamma;
+  const int* shift;
+  int R_own, R_prev, n, M, bc, fe, stages, wrap, B, H;
+  double dt, a_2h, nu_h2, divisor;
+};
+
+__device__ __forceinline__ void store_row(double* p, double v, bool nt) {
+  if (nt)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 template <int J, int T>
-__device__ __forceinline__ void level_step(const Lvl1D* __restrict__ Lp, int chunk, int64_t m,
-                                           double* lds) {
-  const Lvl1D& L = *Lp;
+__device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, double* lds,
+                                           bool nt_store) {
   Geo G;
   G.n = L.n;
   G.M = L.M;
@@ -165,7 +183,8 @@ __device__ __forceinline__ void level_step(const Lvl1D* __restrict__ Lp, int chu
       d0 = d1;
       d1 = t;
     }
-    for (int l = l0 + threadIdx.x; l < l1; l += T) S.out[per ? l : l - 1] = d0[l] / divisor;
+    for (int l = l0 + threadIdx.x; l < l1; l += T)
+      store_row(S.out + (per ? l : l - 1), d0[l] / divisor, nt_store);
     return;
   }
 
@@ -195,7 +214,26 @@ __device__ __forceinline__ void level_step(const Lvl1D* __restrict__ Lp, int chu
   const int last = per ? n : n + 1;                   // one past the last physical row of g
   for (int l = H + threadIdx.x; l < H + B; l += T) {
     const int g = g0 - H + l;
-    if (g < last) S.out[per ? g : g - 1] = d0[l] / divisor;
+    if (g < last) store_row(S.out + (per ? g : g - 1), d0[l] / divisor, nt_store);
+  }
+}
+
+template <int T>
+__device__ __forceinline__ void dispatch_level(int j, const View& v, int chunk, int64_t m,
+                                               double* lds, bool nt) {
+  switch (j) {
+    case 0: level_step<0, T>(v, chunk, m, lds, nt); break;
+    case 1: level_step<1, T>(v, chunk, m, lds, nt); break;
+    case 2: level_step<2, T>(v, chunk, m, lds, nt); break;
+    case 3: level_step<3, T>(v, chunk, m, lds, nt); break;
+    case 4: level_step<4, T>(v, chunk, m, lds, nt); break;
+    case 5: level_step<5, T>(v, chunk, m, lds, nt); break;
+    case 6: level_step<6, T>(v, chunk, m, lds, nt); break;
+    case 7: level_step<7, T>(v, chunk, m, lds, nt); break;
+    case 8: level_step<8, T>(v, chunk, m, lds, nt); break;
+    case 9: level_step<9, T>(v, chunk, m, lds, nt); break;
+    case 10: level_step<10, T>(v, chunk, m, lds, nt); break;
+    default: level_step<11, T>(v, chunk, m, lds, nt); break;
   }
 }
 
@@ -208,20 +246,24 @@ __global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
   const int j = L->j;
   const int64_t m = sigma - L->sigma0 - (int64_t)j * (j + 1) / 2;  // time index computed now
   if (m < 1 || m > L->nt) return;                                   // level idle this step
-  switch (j) {
-    case 0: level_step<0, T>(L, bk.chunk, m, lds); break;
-    case 1: level_step<1, T>(L, bk.chunk, m, lds); break;
-    case 2: level_step<2, T>(L, bk.chunk, m, lds); break;
-    case 3: level_step<3, T>(L, bk.chunk, m, lds); break;
-    case 4: level_step<4, T>(L, bk.chunk, m, lds); break;
-    case 5: level_step<5, T>(L, bk.chunk, m, lds); break;
-    case 6: level_step<6, T>(L, bk.chunk, m, lds); break;
-    case 7: level_step<7, T>(L, bk.chunk, m, lds); break;
-    case 8: level_step<8, T>(L, bk.chunk, m, lds); break;
-    case 9: level_step<9, T>(L, bk.chunk, m, lds); break;
-    case 10: level_step<10, T>(L, bk.chunk, m, lds); break;
-    default: level_step<11, T>(L, bk.chunk, m, lds); break;
-  }
+  View v{L->own, L->prev, L->W, L->gamma, L->shift, L->R_own, L->R_prev, L->n, L->M, L->bc,
+         L->fe, L->stages, L->wrap, L->B, L->H, L->dt, L->a_2h, L->nu_h2, L->divisor};
+  dispatch_level<T>(j, v, bk.chunk, m, lds, false);
+}
+
+// A single instance's step with every descriptor in the kernel arguments: block b handles level
+// b / nchunks, chunk b % nchunks, so the first memory access of a block is its data.
+template <int T>
+__global__ __launch_bounds__(T) void k_step1d_solo(const Solo1D a, int64_t sigma) {
+  extern __shared__ double lds[];
+  const int j = blockIdx.x / a.nchunks;
+  const int chunk = blockIdx.x - j * a.nchunks;
+  const int64_t m = sigma - (int64_t)j * (j + 1) / 2;
+  if (m < 1 || m > a.nt) return;
+  View v{a.ring[j], j > 0 ? a.ring[j - 1] : nullptr, a.W[j], a.gamma, a.shift, a.R[j],
+         j > 0 ? a.R[j - 1] : 1, a.n, a.M, a.bc, a.fe, a.stages, a.wrap, a.B, a.H, a.dt,
+         a.a_2h, a.nu_h2, a.divisor};
+  dispatch_level<T>(j, v, chunk, m, lds, a.nt_store != 0);
 }
 
 __global__ void k_nonfinite(const double* __restrict__ x, int64_t count, int* flag) {
@@ -250,6 +292,9 @@ hipError_t allow_lds(size_t lds_bytes) {
   if (lds_bytes > allowed) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step1d<T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step1d_solo<T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
     allowed = lds_bytes;
   }
@@ -290,6 +335,32 @@ hipError_t launch_1d_step(const Lvl1D* d_items, const Blk1D* d_blocks, int nbloc
     case 1024:
       hipLaunchKernelGGL(k_step1d<1024>, dim3(nblocks), dim3(1024), lds_bytes, stream, d_items,
                          d_blocks, sigma);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, size_t lds_bytes,
+                          int64_t sigma, hipStream_t stream) {
+  if (nblocks <= 0) return hipSuccess;
+  switch (threads) {
+    case 64:
+      hipLaunchKernelGGL(k_step1d_solo<64>, dim3(nblocks), dim3(64), lds_bytes, stream, a, sigma);
+      break;
+    case 128:
+      hipLaunchKernelGGL(k_step1d_solo<128>, dim3(nblocks), dim3(128), lds_bytes, stream, a, sigma);
+      break;
+    case 256:
+      hipLaunchKernelGGL(k_step1d_solo<256>, dim3(nblocks), dim3(256), lds_bytes, stream, a, sigma);
+      break;
+    case 512:
+      hipLaunchKernelGGL(k_step1d_solo<512>, dim3(nblocks), dim3(512), lds_bytes, stream, a, sigma);
+      break;
+    case 1024:
+      hipLaunchKernelGGL(k_step1d_solo<1024>, dim3(nblocks), dim3(1024), lds_bytes, stream, a,
+                         sigma);
       break;
     default:
       return hipErrorInvalidValue;

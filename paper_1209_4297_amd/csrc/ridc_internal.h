@@ -76,6 +76,18 @@ struct Lvl1D {
   int32_t shift[kMaxPcr];  // 2^k mod M
 };
 
+// The descriptor of a single instance's step, passed by value in the kernel arguments.
+struct Solo1D {
+  double* ring[kMaxOrder];     // level rings
+  const double* W[kMaxOrder];  // weights per level (j rows x (j+1))
+  const double* gamma;         // PCR stage coefficients (device)
+  const int32_t* shift;        // PCR stage shifts (device)
+  int32_t R[kMaxOrder];        // ring slots per level
+  int64_t nt;
+  int32_t nchunks, n, M, bc, fe, stages, wrap, B, H, nt_store;
+  double dt, a_2h, nu_h2, divisor;
+};
+
 struct Blk1D {
   int32_t item;
   int32_t chunk;
@@ -88,6 +100,11 @@ hipError_t prepare_1d_step(int threads, size_t lds_bytes);
 // Launch one pipeline step of a grouped 1D batch.
 hipError_t launch_1d_step(const Lvl1D* d_items, const Blk1D* d_blocks, int nblocks, int threads,
                           size_t lds_bytes, int64_t sigma, hipStream_t stream);
+
+// Launch one pipeline step of a single instance (descriptor in the kernel arguments); block b
+// covers level b / nchunks, chunk b % nchunks.
+hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, size_t lds_bytes,
+                          int64_t sigma, hipStream_t stream);
 
 // Set *flag to 1 if any of x[0..count) is not finite.
 hipError_t launch_nonfinite_check(const double* x, int64_t count, int* flag, hipStream_t stream);

@@ -69,8 +69,9 @@ def _load():
         "ridc_step_cost": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]),
         "ridc_version": (ctypes.c_char_p, []),
-        "ridc_autotune": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
-        "ridc_set_tile": (ctypes.c_int, [vp, i32, i32]),
+        "ridc_autotune": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                         ctypes.POINTER(i32)]),
+        "ridc_set_tile": (ctypes.c_int, [vp, i32, i32, i32]),
         "ridc_kernel_time": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_double)]),
     }
@@ -198,14 +199,16 @@ class Ridc:
         _check(_lib.ridc_sync(self._h))
 
     def autotune(self):
-        """Pick the fastest tiling (1D); the handle must be re-armed afterwards."""
+        """Pick the fastest tiling (1D); the handle must be re-armed afterwards.
+        Returns (threads, rows, flags)."""
         t = ctypes.c_int32()
         r = ctypes.c_int32()
-        _check(_lib.ridc_autotune(self._h, ctypes.byref(t), ctypes.byref(r)))
-        return t.value, r.value
+        f = ctypes.c_int32()
+        _check(_lib.ridc_autotune(self._h, ctypes.byref(t), ctypes.byref(r), ctypes.byref(f)))
+        return t.value, r.value, f.value
 
-    def set_tile(self, threads: int, rows: int):
-        _check(_lib.ridc_set_tile(self._h, int(threads), int(rows)))
+    def set_tile(self, threads: int, rows: int, flags: int = 0):
+        _check(_lib.ridc_set_tile(self._h, int(threads), int(rows), int(flags)))
 
     def kernel_time(self, reps: int = 50):
         """(us per launch, algorithmic work per launch) of the dominant kernel at the next

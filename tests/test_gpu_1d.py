@@ -211,18 +211,19 @@ def test_tilings_are_bitwise_identical(env):
     x0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
     s = ridc.Ridc(prob)
     outs = []
-    tiles = [(256, 0), (1024, 0), (256, 1024), (512, 512), (128, 2048), (1024, 256)]
-    for threads, rows in tiles:
+    tiles = [(256, 0, 0), (1024, 0, 1), (256, 1024, 0), (512, 512, 1), (128, 2048, 0),
+             (1024, 256, 1)]
+    for threads, rows, flags in tiles:
         try:
-            s.set_tile(threads, rows)
+            s.set_tile(threads, rows, flags)
         except ridc.RidcError:
             continue
-        _say(f"tile threads={threads} rows={rows}")
+        _say(f"tile threads={threads} rows={rows} flags={flags}")
         outs.append(s.integrate(x0, prob["nt"]).cpu().numpy())
     assert len(outs) >= 4
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
-    t, r = s.autotune()
-    _say(f"autotuned: threads={t} rows={r}")
+    t, r, f = s.autotune()
+    _say(f"autotuned: threads={t} rows={r} flags={f}")
     np.testing.assert_array_equal(s.integrate(x0, prob["nt"]).cpu().numpy(), outs[0])
     s.close()
