@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="reacdiff1d",
-                    choices=["reacdiff1d", "advdiff1d", "reacdiff2d", "batched1d", "serving"])
+                    choices=["reacdiff1d", "advdiff1d", "reacdiff2d", "batched1d", "serving",
+                             "paper_advdiff", "paper_burgers"])
     ap.add_argument("--horizon", type=float, default=10.0,
                     help="serving: seconds of Poisson arrivals admitted")
     ap.add_argument("--max-wall", type=float, default=40.0,
@@ -125,6 +126,17 @@ def bench_1d(args, torch, ridc, which):
         desc = ("1D reaction-diffusion u_t = nu u_xx + u(1-u), Dirichlet [0,1], N=8192, "
                 "nu=1e-3, 8 seeded Gaussians, RIDC order 4, T=1, Nt=2000, FP64")
         steps, warmup = args.steps or 20, args.warmup if args.warmup is not None else 3
+    elif which == "paper_advdiff":
+        prob, u0 = workloads.config_paper_advdiff()
+        desc = ("paper section IV-A: u_t = 0.1 u_x + 1e-3 u_xx, periodic [0,1], dx=1/1000, "
+                "first-order upwind advection, u0=2+sin 2pi x, RIDC order 4, T=40, Nt=4000, FP64")
+        steps, warmup = args.steps or 10, args.warmup if args.warmup is not None else 2
+    elif which == "paper_burgers":
+        prob, u0 = workloads.config_paper_burgers()
+        desc = ("paper section IV-B: u_t + (u^2/2)_x = 1e-3 u_xx, Dirichlet [0,1], dx=1/1000, "
+                "flux F=(u_{i+1}^2+u_i^2)/2, u0=sin 2pi x + sin(pi x)/2, RIDC order 4, T=1, "
+                "Nt=1000, FP64")
+        steps, warmup = args.steps or 20, args.warmup if args.warmup is not None else 3
     else:
         prob, u0 = workloads.config_advdiff_1d()
         desc = ("1D advection-diffusion u_t + u_x = 0.1 u_xx, periodic [0,2pi), N=128, "
@@ -137,7 +149,7 @@ def bench_1d(args, torch, ridc, which):
     cpu = rel = None
     if not args.no_cpu:
         from oracle import Problem, rel_l2, ridc_pipelined
-        reps = 1 if which == "reacdiff1d" else 20
+        reps = 20 if which == "advdiff1d" else 1
         ref, sec = oracle_time(lambda: [ridc_pipelined(Problem.from_dict(prob), u0, nt, P)[-1]
                                         for _ in range(reps)][-1])
         rel = rel_l2(out, ref)
@@ -350,7 +362,7 @@ def main():
 
 
 def run_workload(args, torch, ridc):
-    if args.workload in ("reacdiff1d", "advdiff1d"):
+    if args.workload in ("reacdiff1d", "advdiff1d", "paper_advdiff", "paper_burgers"):
         r = bench_1d(args, torch, ridc, args.workload)
     elif args.workload == "reacdiff2d":
         r = bench_2d(args, torch, ridc)

@@ -55,9 +55,13 @@ typedef enum { RIDC_BC_PERIODIC = 0, RIDC_BC_DIRICHLET0 = 1 } ridc_bc;
 
 /* Explicit (non-stiff) term f_E, section II: f^N.                                            */
 typedef enum {
-  RIDC_FE_NONE = 0,       /* f_E = 0                                                          */
-  RIDC_FE_ADVECT_C2 = 1,  /* f_E = -a (u_{i+1} - u_{i-1}) / (2h), 1D only                     */
-  RIDC_FE_LOGISTIC = 2    /* f_E = u (1 - u), pointwise                                        */
+  RIDC_FE_NONE = 0,          /* f_E = 0                                                       */
+  RIDC_FE_ADVECT_C2 = 1,     /* f_E = -a (u_{i+1} - u_{i-1}) / (2h), 1D only                  */
+  RIDC_FE_LOGISTIC = 2,      /* f_E = u (1 - u), pointwise                                     */
+  RIDC_FE_ADVECT_UPWIND = 3, /* f_E = -a (u_i - u_{i-1}) / h if a >= 0, else -a (u_{i+1} - u_i)
+                                / h: first-order upwind (section IV-A), 1D only               */
+  RIDC_FE_BURGERS = 4        /* f_E = -(1/2)(F_{i+1/2} - F_{i-1/2}) / h, F_{i+1/2} =
+                                (u_{i+1}^2 + u_i^2)/2: the numerical flux of section IV-B, 1D */
 } ridc_fe_kind;
 
 /* Arithmetic of the implicit solve.  Quadrature sums and level differences are FP64 always.  */
@@ -108,6 +112,13 @@ size_t ridc_footprint_bytes(const ridc_problem* p);
  * u0_dev and uT_dev may be the same array.  Asynchronous; see ridc_sync.                      */
 int ridc_integrate(ridc_handle* h, const double* u0_dev, int64_t nsteps, double* uT_dev,
                    double* levels_dev);
+
+/* RIDC with restarts (section III-E): nsteps is split into `segments` equal intervals (nsteps
+ * must be a multiple of segments, each segment >= order-1 steps); each interval is a full RIDC
+ * integration restarted from the top level of the previous one.  segments = 1 is
+ * ridc_integrate.  uT_dev receives the final top level (it may alias u0_dev).                 */
+int ridc_integrate_restarts(ridc_handle* h, const double* u0_dev, int64_t nsteps,
+                            int32_t segments, double* uT_dev);
 
 /* Integrate `count` handles (any mix of sizes, orders, dims and precisions, all created on the
  * same stream) together: each pipeline step of every handle is grouped into shared launches.

@@ -11,7 +11,8 @@ What it computes (every step written out in plain NumPy/SciPy, FP64, no blocking
 
 * The IVP ``y' = f^S(y) + f^N(y)`` (section II, eq. ode) with the stiff part linear,
   ``f^S(y) = nu * Lap_h y`` (the diffusion operator, section IV), and the non-stiff part
-  ``f^N`` one of: none, centred advection ``-a u_x``, or the logistic reaction ``u(1-u)``.
+  ``f^N`` one of: none, centred or first-order upwind advection ``-a u_x`` (section IV-A),
+  the Burgers numerical flux (section IV-B), or the logistic reaction ``u(1-u)``.
 * Level 0, the predictor: first-order IMEX (forward-backward) Euler, section II
   eq. (imex_diffusion) and section III-B eq. (pred):
   ``(I - dt D) eta[0]_{n+1} = eta[0]_n + dt f^N(eta[0]_n)``.
@@ -29,6 +30,7 @@ What it computes (every step written out in plain NumPy/SciPy, FP64, no blocking
   weights (``k = 0..j-1``) is read as ``k = 0..j``, matching the sums they enter.
 * Every level starts from the initial data (section III-E, Fig. 2 caption).
 * Output: the final value of every level; the top level is the most accurate (section III-E).
+* Restarts (section III-E): equal segments, each restarted from the top level of the previous.
 
 Solvers for ``(I - dt nu Lap_h) x = b`` (the paper pre-factors this matrix by QR; any exact
 solver gives the same values up to rounding): FFT diagonalisation of the circulant (periodic
@@ -59,6 +61,7 @@ __all__ = [
     "ridc_sequential",
     "ridc_pipelined",
     "ridc",
+    "ridc_restarted",
     "fbe",
     "rel_l2",
 ]
@@ -173,15 +176,35 @@ def f_implicit(p: Problem, u: np.ndarray) -> np.ndarray:
 
 
 def f_explicit(p: Problem, u: np.ndarray) -> np.ndarray:
-    """``f^N(u)``: none, centred advection ``-a (u_{i+1} - u_{i-1}) / (2h)`` (1D), or ``u(1-u)``."""
+    """``f^N(u)`` for ``u_t + a u_x = ...`` and friends:
+
+    * ``none``: 0;
+    * ``logistic``: ``u(1-u)``;
+    * ``advect`` (1D): centred ``-a (u_{i+1} - u_{i-1}) / (2h)``;
+    * ``upwind`` (1D, section IV-A): first-order upwind ``-a (u_i - u_{i-1}) / h`` for
+      ``a >= 0`` and ``-a (u_{i+1} - u_i) / h`` for ``a < 0`` (the paper's ``u_t = c u_x`` is
+      ``a = -c``);
+    * ``burgers`` (1D, section IV-B): ``-(1/2)(f_{i+1/2} - f_{i-1/2}) / h`` with the flux
+      ``f_{i+1/2} = (u_{i+1}^2 + u_i^2) / 2``.
+    """
     if p.fe == "none":
         return np.zeros_like(u)
     if p.fe == "logistic":
         return u * (1.0 - u)
+    if p.fe in ("advect", "upwind", "burgers") and p.dim != 1:
+        raise ValueError(f"{p.fe} is defined for 1D problems")
+    up = _shift(p, u, 1, 0)
+    um = _shift(p, u, -1, 0)
     if p.fe == "advect":
-        if p.dim != 1:
-            raise ValueError("advection is defined for 1D problems")
-        return -p.a * (_shift(p, u, 1, 0) - _shift(p, u, -1, 0)) / (2.0 * p.h)
+        return -p.a * (up - um) / (2.0 * p.h)
+    if p.fe == "upwind":
+        if p.a >= 0:
+            return -p.a * (u - um) / p.h
+        return -p.a * (up - u) / p.h
+    if p.fe == "burgers":
+        flux_right = 0.5 * (up * up + u * u)        # f_{i+1/2}
+        flux_left = 0.5 * (u * u + um * um)         # f_{i-1/2}
+        return -0.5 * (flux_right - flux_left) / p.h
     raise ValueError(f"unknown explicit term {p.fe!r}")
 
 
@@ -319,6 +342,18 @@ def ridc_pipelined(p: Problem, u0: np.ndarray, nt: int, order: int, trace=None) 
 def ridc(p: Problem, u0: np.ndarray, nt: int, order: int) -> np.ndarray:
     """Top-level (most accurate) RIDC solution at ``t = nt * dt``."""
     return ridc_pipelined(p, u0, nt, order)[-1]
+
+
+def ridc_restarted(p: Problem, u0: np.ndarray, nt: int, order: int, segments: int) -> np.ndarray:
+    """RIDC with restarts (section III-E): the nt steps are split into ``segments`` equal
+    intervals; each is a full RIDC integration started from the most accurate (top) level of
+    the previous one."""
+    if segments < 1 or nt % segments:
+        raise ValueError("nt must be a positive multiple of segments")
+    u = np.asarray(u0, dtype=np.float64)
+    for _ in range(segments):
+        u = ridc_pipelined(p, u, nt // segments, order)[-1]
+    return u
 
 
 def fbe(p: Problem, u0: np.ndarray, nt: int) -> np.ndarray:

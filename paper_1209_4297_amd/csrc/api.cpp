@@ -94,7 +94,7 @@ int validate(const ridc_problem* p) {
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(RIDC_E_INVAL, "dt must be > 0");
   if (!(p->nu >= 0.0) || !std::isfinite(p->nu)) return fail(RIDC_E_INVAL, "nu must be >= 0");
   if (!std::isfinite(p->a)) return fail(RIDC_E_INVAL, "a must be finite");
-  if (p->fe_kind < RIDC_FE_NONE || p->fe_kind > RIDC_FE_LOGISTIC)
+  if (p->fe_kind < RIDC_FE_NONE || p->fe_kind > RIDC_FE_BURGERS)
     return fail(RIDC_E_INVAL, "unknown explicit term");
   if (p->prec < RIDC_PREC_FP64 || p->prec > RIDC_PREC_BF16X3_REFINE)
     return fail(RIDC_E_INVAL, "unknown precision");
@@ -102,8 +102,8 @@ int validate(const ridc_problem* p) {
   if (p->dim == 2) {
     if (p->bc != RIDC_BC_DIRICHLET0)
       return fail(RIDC_E_UNSUPPORTED, "2D supports Dirichlet boundaries only");
-    if (p->fe_kind == RIDC_FE_ADVECT_C2)
-      return fail(RIDC_E_UNSUPPORTED, "2D advection is not provided");
+    if (p->fe_kind != RIDC_FE_NONE && p->fe_kind != RIDC_FE_LOGISTIC)
+      return fail(RIDC_E_UNSUPPORTED, "2D provides pointwise explicit terms only");
     return plan2d_validate(p);
   }
   if (p->prec != RIDC_PREC_FP64) return fail(RIDC_E_UNSUPPORTED, "1D computes in FP64 only");
@@ -266,7 +266,7 @@ void build_items_1d(ridc_handle* h, const Tile1D& tile) {
     it.H = H;
     it.nchunks = nchunks;
     it.dt = p.dt;
-    it.a_2h = p.a / (2.0 * h->h);
+    it.ce = explicit_coeff(p.fe_kind, p.a, h->h);
     it.nu_h2 = p.nu / (h->h * h->h);
     it.divisor = h->pcr.divisor;
     for (int k = 0; k < h->pcr.stages; ++k) {
@@ -303,7 +303,7 @@ void build_items_1d(ridc_handle* h, const Tile1D& tile) {
   a.H = H;
   a.nt_store = tile.nt_store;
   a.dt = p.dt;
-  a.a_2h = p.a / (2.0 * h->h);
+  a.ce = explicit_coeff(p.fe_kind, p.a, h->h);
   a.nu_h2 = p.nu / (h->h * h->h);
   a.divisor = h->pcr.divisor;
   h->solo_blocks = P * nchunks;
@@ -763,6 +763,23 @@ int ridc_integrate(ridc_handle* h, const double* u0_dev, int64_t nsteps, double*
     if (rc != RIDC_OK) return rc;
   }
   return ridc_read(h, uT_dev, levels_dev);
+}
+
+int ridc_integrate_restarts(ridc_handle* h, const double* u0_dev, int64_t nsteps,
+                            int32_t segments, double* uT_dev) {
+  if (!h || !u0_dev || !uT_dev) return fail(RIDC_E_INVAL, "NULL argument");
+  if (segments < 1 || nsteps < 0 || nsteps % segments != 0)
+    return fail(RIDC_E_INVAL, "nsteps must be a non-negative multiple of segments");
+  const int64_t seg = nsteps / segments;
+  // each segment restarts from the previous top level, held in uT (u0 and uT may alias: every
+  // segment loads its start value into the rings before anything writes uT)
+  const double* src = u0_dev;
+  for (int32_t k = 0; k < segments; ++k) {
+    int rc = ridc_integrate(h, src, seg, uT_dev, nullptr);
+    if (rc != RIDC_OK) return rc;
+    src = uT_dev;
+  }
+  return RIDC_OK;
 }
 
 int ridc_integrate_batch(ridc_handle* const* hs, int32_t count, const double* const* u0,

@@ -28,10 +28,17 @@ namespace ridc {
 
 namespace {
 
-__device__ __forceinline__ double fe_eval(int fe, double a_2h, double um, double u0, double up) {
-  if (fe == RIDC_FE_ADVECT_C2) return -a_2h * (up - um);
+// f_E at one point from its neighbours; ce is explicit_coeff(fe, a, h).
+__device__ __forceinline__ double fe_eval(int fe, double ce, double um, double u0, double up) {
+  if (fe == RIDC_FE_ADVECT_C2) return -ce * (up - um);
   if (fe == RIDC_FE_LOGISTIC) return u0 * (1.0 - u0);
+  if (fe == RIDC_FE_ADVECT_UPWIND) return ce >= 0.0 ? -ce * (u0 - um) : -ce * (up - u0);
+  if (fe == RIDC_FE_BURGERS) return -ce * (up * up - um * um);
   return 0.0;
+}
+
+__device__ __forceinline__ bool fe_stencil(int fe) {
+  return fe == RIDC_FE_ADVECT_C2 || fe == RIDC_FE_ADVECT_UPWIND || fe == RIDC_FE_BURGERS;
 }
 
 // v at physical row p (-1 <= p <= n) under the grid's boundary rule
@@ -58,7 +65,7 @@ struct Step {
 struct Geo {        // scalar problem data of a work item, copied out of the descriptor
   int n, M, fe;
   bool per;
-  double dt, a_2h, nu_h2;
+  double dt, ce, nu_h2;
 };
 
 template <int J>
@@ -66,11 +73,11 @@ __device__ __forceinline__ double rhs_row(const Geo& G, const Step<J>& S, int p)
   const int n = G.n;
   const double u0 = S.u[p];
   double um = 0.0, up = 0.0;
-  if (G.fe == RIDC_FE_ADVECT_C2) {
+  if (fe_stencil(G.fe)) {
     um = at(S.u, p - 1, n, G.per);
     up = at(S.u, p + 1, n, G.per);
   }
-  double acc = u0 + G.dt * fe_eval(G.fe, G.a_2h, um, u0, up);
+  double acc = u0 + G.dt * fe_eval(G.fe, G.ce, um, u0, up);
   if constexpr (J > 0) {
 #pragma unroll
     for (int i = 0; i <= J; ++i) {
@@ -79,7 +86,7 @@ __device__ __forceinline__ double rhs_row(const Geo& G, const Step<J>& S, int p)
       const double v0 = v[p];
       const double vp = at(v, p + 1, n, G.per);
       const double li = G.nu_h2 * ((vm + vp) - 2.0 * v0);
-      acc += S.cf[i] * fe_eval(G.fe, G.a_2h, vm, v0, vp) + S.cl[i] * li;
+      acc += S.cf[i] * fe_eval(G.fe, G.ce, vm, v0, vp) + S.cl[i] * li;
     }
   }
   return acc;
@@ -103,7 +110,7 @@ struct View {
   const double* gamma;
   const int* shift;
   int R_own, R_prev, n, M, bc, fe, stages, wrap, B, H;
-  double dt, a_2h, nu_h2, divisor;
+  double dt, ce, nu_h2, divisor;
 };
 
 __device__ __forceinline__ void store_row(double* p, double v, bool nt) {
@@ -122,7 +129,7 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
   G.fe = L.fe;
   G.per = L.bc == RIDC_BC_PERIODIC;
   G.dt = L.dt;
-  G.a_2h = L.a_2h;
+  G.ce = L.ce;
   G.nu_h2 = L.nu_h2;
   const int n = G.n, M = G.M;
   const bool per = G.per;
@@ -247,7 +254,7 @@ __global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
   const int64_t m = sigma - L->sigma0 - (int64_t)j * (j + 1) / 2;  // time index computed now
   if (m < 1 || m > L->nt) return;                                   // level idle this step
   View v{L->own, L->prev, L->W, L->gamma, L->shift, L->R_own, L->R_prev, L->n, L->M, L->bc,
-         L->fe, L->stages, L->wrap, L->B, L->H, L->dt, L->a_2h, L->nu_h2, L->divisor};
+         L->fe, L->stages, L->wrap, L->B, L->H, L->dt, L->ce, L->nu_h2, L->divisor};
   dispatch_level<T>(j, v, bk.chunk, m, lds, false);
 }
 
@@ -262,7 +269,7 @@ __global__ __launch_bounds__(T) void k_step1d_solo(const Solo1D a, int64_t sigma
   if (m < 1 || m > a.nt) return;
   View v{a.ring[j], j > 0 ? a.ring[j - 1] : nullptr, a.W[j], a.gamma, a.shift, a.R[j],
          j > 0 ? a.R[j - 1] : 1, a.n, a.M, a.bc, a.fe, a.stages, a.wrap, a.B, a.H, a.dt,
-         a.a_2h, a.nu_h2, a.divisor};
+         a.ce, a.nu_h2, a.divisor};
   dispatch_level<T>(j, v, chunk, m, lds, a.nt_store != 0);
 }
 

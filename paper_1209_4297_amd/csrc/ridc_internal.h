@@ -12,7 +12,16 @@
 
 namespace ridc {
 
-constexpr int kMaxPcr = 48;          // PCR stages kept in a level descriptor
+constexpr int kMaxPcr = 48;
+
+// Coefficient of the explicit stencil of f_E: a/(2h) (centred advection), a/h (upwind),
+// 1/(4h) (Burgers flux), unused otherwise.
+inline double explicit_coeff(int fe, double a, double h) {
+  if (fe == RIDC_FE_ADVECT_C2) return a / (2.0 * h);
+  if (fe == RIDC_FE_ADVECT_UPWIND) return a / h;
+  if (fe == RIDC_FE_BURGERS) return 1.0 / (4.0 * h);
+  return 0.0;
+}          // PCR stages kept in a level descriptor
 constexpr int kMaxOrder = RIDC_MAX_ORDER;
 
 // ---------------------------------------------------------------------------------------------
@@ -69,7 +78,7 @@ struct Lvl1D {
   int32_t H;               // halo rows each side (chunk mode) = 2^stages - 1
   int32_t nchunks;
   double dt;
-  double a_2h;             // a / (2h)
+  double ce;               // coefficient of the explicit stencil (see explicit_coeff)
   double nu_h2;            // nu / h^2
   double divisor;          // final PCR divisor
   double gamma[kMaxPcr];
@@ -85,7 +94,7 @@ struct Solo1D {
   int32_t R[kMaxOrder];        // ring slots per level
   int64_t nt;
   int32_t nchunks, n, M, bc, fe, stages, wrap, B, H, nt_store;
-  double dt, a_2h, nu_h2, divisor;
+  double dt, ce, nu_h2, divisor;
 };
 
 struct Blk1D {

@@ -22,7 +22,7 @@ RIDC_E_NONFINITE = -5
 RIDC_E_STATE = -6
 
 BC = {"periodic": 0, "dirichlet": 1}
-FE = {"none": 0, "advect": 1, "logistic": 2}
+FE = {"none": 0, "advect": 1, "logistic": 2, "upwind": 3, "burgers": 4}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 _ERR_NAMES = {-1: "RIDC_E_INVAL", -2: "RIDC_E_UNSUPPORTED", -3: "RIDC_E_NOMEM",
@@ -74,6 +74,7 @@ def _load():
         "ridc_set_tile": (ctypes.c_int, [vp, i32, i32, i32]),
         "ridc_kernel_time": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_double)]),
+        "ridc_integrate_restarts": (ctypes.c_int, [vp, dp, i64, i32, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -87,7 +88,7 @@ EXPORTED = ("ridc_create", "ridc_destroy", "ridc_footprint_bytes", "ridc_integra
             "ridc_integrate_batch", "ridc_begin", "ridc_advance", "ridc_remaining", "ridc_read",
             "ridc_sync", "ridc_last_error", "ridc_quadrature_weights", "ridc_pcr_plan",
             "ridc_step_cost", "ridc_version", "ridc_autotune", "ridc_set_tile",
-            "ridc_kernel_time")
+            "ridc_kernel_time", "ridc_integrate_restarts")
 
 
 def lib():
@@ -182,6 +183,16 @@ class Ridc:
         if uT is None:
             uT = torch.empty_like(u0)
         _check(_lib.ridc_integrate(self._h, _ptr(u0), int(nsteps), _ptr(uT), _ptr(levels)))
+        if sync:
+            self.sync()
+        return uT
+
+    def integrate_restarts(self, u0, nsteps: int, segments: int, uT=None, sync: bool = True):
+        import torch
+        if uT is None:
+            uT = torch.empty_like(u0)
+        _check(_lib.ridc_integrate_restarts(self._h, _ptr(u0), int(nsteps), int(segments),
+                                            _ptr(uT)))
         if sync:
             self.sync()
         return uT

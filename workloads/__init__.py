@@ -13,8 +13,9 @@ Problem dictionaries use these keys:
 ``n``        unknowns per axis (periodic: points ``x_i = i*h``, ``h = length/n``;
              Dirichlet: interior points ``x_i = i*h``, ``i = 1..n``, ``h = length/(n+1)``)
 ``length``   domain length per axis
-``fe``       explicit term: ``"none"``, ``"advect"`` (``-a u_x``, centred) or ``"logistic"``
-             (``u(1-u)``)
+``fe``       explicit term: ``"none"``, ``"advect"`` (``-a u_x``, centred), ``"upwind"``
+             (``-a u_x``, first-order upwind), ``"burgers"`` (``-(u^2/2)_x``, flux form) or
+             ``"logistic"`` (``u(1-u)``)
 ``a``        advection speed (``fe == "advect"``)
 ``nu``       diffusion coefficient of the implicit term ``nu * Laplacian``
 ``T``        final time
@@ -37,6 +38,8 @@ __all__ = [
     "config_reacdiff_2d",
     "config_batched_1d",
     "serving_requests",
+    "config_paper_advdiff",
+    "config_paper_burgers",
     "SEED_BASE",
 ]
 
@@ -179,3 +182,21 @@ def serving_requests(rate: float = 200.0, duration: float = 60.0,
         if max_requests is not None and len(out) >= max_requests:
             break
     return out
+
+
+def config_paper_advdiff(n: int = 1000, nt: int = 4000, order: int = 4, T: float = 40.0):
+    """The paper's advection-diffusion case: u_t = c u_x + d u_xx, c = 0.1, d = 1e-3, periodic
+    on [0, 1], dx = 1/1000, u0 = 2 + sin(2 pi x), first-order upwind advection (a = -c)."""
+    prob = dict(dim=1, bc="periodic", n=n, length=1.0, fe="upwind", a=-0.1, nu=1e-3,
+                T=T, nt=nt, order=order)
+    x = grid_points("periodic", n, 1.0)
+    return prob, 2.0 + np.sin(2.0 * math.pi * x)
+
+
+def config_paper_burgers(n: int = 999, nt: int = 1000, order: int = 4, T: float = 1.0):
+    """The paper's viscous Burgers case: u_t + (u^2/2)_x = eps u_xx, eps = 1e-3, u = 0 at
+    x = 0, 1, dx = 1/1000 (999 interior points), u0 = sin(2 pi x) + sin(pi x)/2."""
+    prob = dict(dim=1, bc="dirichlet", n=n, length=1.0, fe="burgers", a=0.0, nu=1e-3,
+                T=T, nt=nt, order=order)
+    x = grid_points("dirichlet", n, 1.0)
+    return prob, np.sin(2.0 * math.pi * x) + 0.5 * np.sin(math.pi * x)
