@@ -179,12 +179,15 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32
  * Errors: RIDC_E_INVAL if the tiling does not fit.                                            */
 int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags);
 
-/* Average duration of the dominant kernel, from HIP events on the handle's stream around `reps`
- * back-to-back launches of the handle's next pipeline step (which must have every level
- * active): the fused level step (1D) or the first transform pass over all levels (2D).  The
- * launches recompute the same values (every launch reads inputs it does not write); the handle
- * does not advance.  *work_per_launch (nullable) receives the algorithmic HBM bytes (1D) or
- * flops (2D) of one launch.  Errors: RIDC_E_STATE if the next step is not a full one.        */
+/* Average duration of the dominant kernel per pipeline step, from HIP events on the handle's
+ * stream, starting at the handle's next pipeline step (which must have every level active):
+ *  - 1D, one launch per step: `reps` back-to-back launches of that step (each recomputes the
+ *    same values; the handle does not advance);
+ *  - 1D, whole-integration workgroup (systems that fit one CU's LDS): one launch running
+ *    `reps` steps; the handle runs ahead and is left unarmed (call ridc_begin again);
+ *  - 2D: `reps` launches of the first transform pass over all levels.
+ * *work_per_launch (nullable) receives the algorithmic HBM bytes (1D, per step) or flops (2D,
+ * per pass).  Errors: RIDC_E_STATE if the next step is not a full one or too few remain.     */
 int ridc_kernel_time(ridc_handle* h, int32_t reps, double* us_per_launch,
                      double* work_per_launch);
 

@@ -62,6 +62,13 @@ struct ridc_handle {
   Blk1D* d_blocks = nullptr;
   Solo1D solo{};              // kernel-argument descriptor of a single-instance launch
   int solo_blocks = 0;
+  // fused integration (one workgroup per instance) when the levels fit one CU's LDS
+  bool fused = false;
+  bool fused_db = false;
+  int fused_rpt = 0;
+  size_t fused_lds = 0;
+  Fused1D fused_item{};
+  Fused1D* d_fused = nullptr;
   size_t blocks_cap = 0;
   size_t lds = 0;
 
@@ -161,12 +168,52 @@ int64_t halo_rows(const PcrPlan& pcr) {
   return pcr.stages < 30 ? ((int64_t)1 << pcr.stages) - 1 : ((int64_t)1 << 40);
 }
 
+// Fused integration plan: P level groups of G threads (whole waves) in one workgroup, each
+// level's cycle in LDS: two buffers and 1024 threads when they fit, else one buffer, 512
+// threads and the new values staged in registers (at most 32 rows per thread).
+struct FusedPlan {
+  bool ok = false, db = false;
+  int group = 0, rpt = 0;
+  size_t lds = 0;
+};
+
+FusedPlan plan_fused(const ridc_problem* p) {
+  FusedPlan f;
+  if (p->dim != 1 || p->order > kMaxJ1024 + 1) return f;
+  const int P = p->order;
+  const int64_t ms = p->bc == RIDC_BC_PERIODIC ? p->n : p->n + 2;
+  const int64_t rows = p->n;
+  const size_t maxl = (size_t)device_max_lds();
+  // two buffers per level, 1024 threads
+  const int G1 = (1024 / P) / 64 * 64;
+  if ((size_t)P * 2 * ms * sizeof(double) <= maxl && rows <= (int64_t)G1 * 64) {
+    f.ok = f.db = true;
+    f.group = G1;
+    f.lds = (size_t)P * 2 * ms * sizeof(double);
+    return f;
+  }
+  // one buffer per level, 512 threads, rows staged in registers
+  const int G2 = (512 / P) / 64 * 64;
+  if (G2 < 64 || (size_t)P * ms * sizeof(double) > maxl) return f;
+  const int64_t need = (rows + G2 - 1) / G2;
+  for (int r : {4, 8, 16, 32})
+    if (need <= r) {
+      f.ok = true;
+      f.group = G2;
+      f.rpt = r;
+      f.lds = (size_t)P * ms * sizeof(double);
+      return f;
+    }
+  return f;
+}
+
 bool tile_fits(const ridc_problem* p, const PcrPlan& pcr, const Tile1D& t) {
   const int64_t M = p->bc == RIDC_BC_PERIODIC ? p->n : 2 * p->n + 2;
   const int64_t ms = p->bc == RIDC_BC_PERIODIC ? p->n : p->n + 2;
   if (t.threads != 64 && t.threads != 128 && t.threads != 256 && t.threads != 512 &&
       t.threads != 1024)
     return false;
+  if (t.threads == 1024 && p->order > kMaxJ1024 + 1) return false;
   if (t.wrap) return 2 * sizeof(double) * (size_t)ms <= (size_t)device_max_lds();
   const int64_t H = halo_rows(pcr);
   if (pcr.exact || H >= M || t.B < 1 || t.B + H > p->n) return false;
@@ -231,7 +278,7 @@ void plan_layout(const ridc_problem* p, const Tile1D* tile, Layout* L) {
     const int64_t nchunks = std::max<int64_t>(tile->wrap ? 1 : (p->n + tile->B - 1) / tile->B,
                                               (p->n + kMinChunk - 1) / kMinChunk);
     L->nblocks = nchunks * P;
-    L->items = align256(sizeof(Lvl1D) * P);
+    L->items = align256(sizeof(Lvl1D) * P) + align256(sizeof(Fused1D));
     L->blocks = align256(sizeof(Blk1D) * (size_t)L->nblocks);
   } else {
     L->ws2d = align256(plan2d_workspace_bytes(p));
@@ -319,11 +366,31 @@ struct BatchArena {
   size_t cap_items = 0, cap_blocks = 0;
   Lvl1D* h_items = nullptr;
   Blk1D* h_blocks = nullptr;
+  Fused1D* d_fused = nullptr;
+  Fused1D* h_fused = nullptr;
+  size_t cap_fused = 0;
   hipEvent_t done = nullptr;
   bool pending = false;
 };
 
 thread_local BatchArena g_arena;
+
+int arena_reserve_fused(size_t n) {
+  // called after arena_reserve (device, event and pending upload handled there)
+  if (n > g_arena.cap_fused) {
+    if (g_arena.d_fused) (void)hipFree(g_arena.d_fused);
+    if (g_arena.h_fused) (void)hipHostFree(g_arena.h_fused);
+    g_arena.d_fused = nullptr;
+    g_arena.h_fused = nullptr;
+    const size_t cap = std::max<size_t>(n, 2 * g_arena.cap_fused);
+    if (hipMalloc(&g_arena.d_fused, cap * sizeof(Fused1D)) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "batch fused table");
+    if (hipHostMalloc(&g_arena.h_fused, cap * sizeof(Fused1D), hipHostMallocDefault) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "batch fused staging");
+    g_arena.cap_fused = cap;
+  }
+  return RIDC_OK;
+}
 
 int arena_reserve(size_t nitems, size_t nblocks) {
   int dev = 0;
@@ -380,7 +447,20 @@ int launch_solo_steps_1d(ridc_handle* h, int64_t first, int64_t last) {
   return RIDC_OK;
 }
 
+// Pipeline steps first..last of one handle in one fused launch.
+int launch_fused_steps(ridc_handle* h, int64_t first, int64_t last) {
+  Fused1D F = h->fused_item;
+  F.nt = h->nt;
+  F.sigma0 = 0;
+  F.sigma_first = first - 1;
+  F.sigma_last = last;
+  RIDC_HIP_TRY(launch_fused_1d(nullptr, &F, 1, h->P, h->fused_db, h->fused_rpt, h->fused_lds,
+                               h->stream));
+  return RIDC_OK;
+}
+
 int run_solo_steps(ridc_handle* h, int64_t first, int64_t last) {
+  if (h->p.dim == 1 && h->fused) return launch_fused_steps(h, first, last);
   if (h->p.dim == 1) return launch_solo_steps_1d(h, first, last);
   Plan2D* pl = h->p2;
   const int64_t before = first - 1;
@@ -549,10 +629,38 @@ int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out) {
   if (p->dim == 1) {
     h->d_items = (Lvl1D*)cur;
     cur += L.items;
+    h->d_fused = (Fused1D*)((char*)h->d_items + align256(sizeof(Lvl1D) * h->P));
     h->d_blocks = (Blk1D*)cur;
     cur += L.blocks;
     h->blocks_cap = (size_t)L.nblocks;
     build_items_1d(h, tile);
+    const FusedPlan fp = plan_fused(p);
+    h->fused = fp.ok && env_flag("RIDC_FUSED", true);
+    h->fused_db = fp.db;
+    h->fused_rpt = fp.rpt;
+    h->fused_lds = fp.lds;
+    {
+      Fused1D& F = h->fused_item;
+      F = Fused1D{};
+      for (int j = 0; j < h->P; ++j) {
+        F.ring[j] = h->ring[j];
+        F.W[j] = j > 0 ? h->W + h->woff[j] : nullptr;
+        F.R[j] = h->R[j];
+      }
+      F.gamma = h->solo.gamma;
+      F.shift = h->solo.shift;
+      F.P = h->P;
+      F.group = fp.group;
+      F.n = (int32_t)p->n;
+      F.M = h->solo.M;
+      F.bc = p->bc;
+      F.fe = p->fe_kind;
+      F.stages = h->pcr.stages;
+      F.dt = p->dt;
+      F.ce = h->solo.ce;
+      F.nu_h2 = h->solo.nu_h2;
+      F.divisor = h->pcr.divisor;
+    }
     if (hipMemcpy(h->d_blocks, h->blocks.data(), sizeof(Blk1D) * h->blocks.size(),
                   hipMemcpyHostToDevice) != hipSuccess) {
       ridc_destroy(h);
@@ -626,6 +734,56 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
   for (int32_t i = 0; i < count; ++i) {
     if (hs[i]->total - hs[i]->sigma <= 0) continue;
     (hs[i]->p.dim == 1 ? h1 : h2).push_back(hs[i]);
+  }
+  // fused-eligible 1D handles: one workgroup each, every requested step in one launch, with the
+  // variant (two LDS buffers, or one buffer and staged rows) that fits all of them
+  {
+    std::vector<ridc_handle*> hf, hs;
+    for (auto* h : h1) (h->fused ? hf : hs).push_back(h);
+    h1.swap(hs);
+    if (!hf.empty()) {
+      rc = arena_reserve(1, 1);
+      if (rc != RIDC_OK) return rc;
+      rc = arena_reserve_fused(hf.size());
+      if (rc != RIDC_OK) return rc;
+      bool db = true;
+      int maxP = 1;
+      for (auto* h : hf) {
+        db = db && h->fused_db;
+        maxP = std::max(maxP, h->P);
+      }
+      int rpt = 0;
+      size_t lds = 0;
+      for (size_t i = 0; i < hf.size(); ++i) {
+        ridc_handle* h = hf[i];
+        const int64_t ms = h->p.bc == RIDC_BC_PERIODIC ? h->p.n : h->p.n + 2;
+        Fused1D F = h->fused_item;
+        if (db) {
+          F.group = (1024 / h->P) / 64 * 64;
+          lds = std::max(lds, (size_t)h->P * 2 * ms * sizeof(double));
+        } else {
+          F.group = (512 / h->P) / 64 * 64;
+          const int64_t need = (h->p.n + F.group - 1) / F.group;
+          int r = 4;
+          while (r < need) r *= 2;
+          rpt = std::max(rpt, r);
+          lds = std::max(lds, (size_t)h->P * ms * sizeof(double));
+        }
+        F.nt = h->nt;
+        F.sigma0 = 0;
+        F.sigma_first = h->sigma;
+        F.sigma_last = std::min(h->total, h->sigma + max_steps);
+        g_arena.h_fused[i] = F;
+      }
+      if (!db && rpt > 32) return fail(RIDC_E_UNSUPPORTED, "fused batch rows per thread");
+      RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_fused, g_arena.h_fused, sizeof(Fused1D) * hf.size(),
+                                  hipMemcpyHostToDevice, stream));
+      RIDC_HIP_TRY(hipEventRecord(g_arena.done, stream));
+      g_arena.pending = true;
+      RIDC_HIP_TRY(launch_fused_1d(g_arena.d_fused, nullptr, (int)hf.size(), maxP, db, rpt, lds,
+                                   stream));
+      for (auto* h : hf) h->sigma = std::min(h->total, h->sigma + max_steps);
+    }
   }
   if (!h1.empty()) {
     size_t nitems = 0, nblocks = 0;
@@ -878,6 +1036,28 @@ int ridc_kernel_time(ridc_handle* h, int32_t reps, double* us_per_launch, double
     if (rc != RIDC_OK) return rc;
     const int passes = h->p.prec == RIDC_PREC_FP64 ? 4 : 8;
     if (work_per_launch) *work_per_launch = flops / passes;   // one pass over every level
+    return RIDC_OK;
+  }
+  if (h->fused) {
+    // the fused kernel runs many steps per launch: time `reps` steps in one launch (the handle
+    // runs ahead, so it is left unarmed)
+    if (s + reps - 1 > h->total) return fail(RIDC_E_STATE, "fewer pipeline steps left than reps");
+    hipEvent_t a, b;
+    RIDC_HIP_TRY(hipEventCreate(&a));
+    RIDC_HIP_TRY(hipEventCreate(&b));
+    (void)hipEventRecord(a, h->stream);
+    rc = launch_fused_steps(h, s, s + reps - 1);
+    (void)hipEventRecord(b, h->stream);
+    float ms = 0;
+    hipError_t e = rc == RIDC_OK ? hipEventSynchronize(b) : hipSuccess;
+    if (rc == RIDC_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    h->nt = -1;
+    if (rc != RIDC_OK) return rc;
+    if (e != hipSuccess) return fail(RIDC_E_HIP, std::string("kernel timing: ") + hipGetErrorString(e));
+    *us_per_launch = 1e3 * (double)ms / reps;
+    if (work_per_launch) *work_per_launch = bytes;
     return RIDC_OK;
   }
   hipEvent_t a, b;

@@ -120,10 +120,9 @@ __device__ __forceinline__ void store_row(double* p, double v, bool nt) {
     *p = v;
 }
 
-template <int J, int T>
-__device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, double* lds,
-                                           bool nt_store) {
-  Geo G;
+// Geometry and this step's window of a level (shared by the per-step and the fused kernels).
+template <int J>
+__device__ __forceinline__ void make_step(const View& L, int64_t m, Geo& G, Step<J>& S) {
   G.n = L.n;
   G.M = L.M;
   G.fe = L.fe;
@@ -131,10 +130,8 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
   G.dt = L.dt;
   G.ce = L.ce;
   G.nu_h2 = L.nu_h2;
-  const int n = G.n, M = G.M;
-  const bool per = G.per;
+  const int n = G.n;
   const int64_t nidx = m - 1;
-  Step<J> S;
   S.u = L.own + (nidx % L.R_own) * (int64_t)n;
   S.out = L.own + (m % L.R_own) * (int64_t)n;
   if constexpr (J > 0) {
@@ -152,6 +149,16 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
       S.cl[i] = G.dt * (wi - (node == nidx + 1 ? 1.0 : 0.0));
     }
   }
+}
+
+template <int J, int T>
+__device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, double* lds,
+                                           bool nt_store) {
+  Geo G;
+  Step<J> S;
+  make_step<J>(L, m, G, S);
+  const int n = G.n, M = G.M;
+  const bool per = G.per;
   const int stages = L.stages;
   const double divisor = L.divisor;
   const double* __restrict__ gam = L.gamma;
@@ -225,6 +232,8 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
   }
 }
 
+// Levels above kMaxJ1024 are not instantiated in 1024-thread kernels (128 registers per
+// thread): the host never sends orders above kMaxJ1024 + 1 to them.
 template <int T>
 __device__ __forceinline__ void dispatch_level(int j, const View& v, int chunk, int64_t m,
                                                double* lds, bool nt) {
@@ -235,12 +244,18 @@ __device__ __forceinline__ void dispatch_level(int j, const View& v, int chunk, 
     case 3: level_step<3, T>(v, chunk, m, lds, nt); break;
     case 4: level_step<4, T>(v, chunk, m, lds, nt); break;
     case 5: level_step<5, T>(v, chunk, m, lds, nt); break;
-    case 6: level_step<6, T>(v, chunk, m, lds, nt); break;
-    case 7: level_step<7, T>(v, chunk, m, lds, nt); break;
-    case 8: level_step<8, T>(v, chunk, m, lds, nt); break;
-    case 9: level_step<9, T>(v, chunk, m, lds, nt); break;
-    case 10: level_step<10, T>(v, chunk, m, lds, nt); break;
-    default: level_step<11, T>(v, chunk, m, lds, nt); break;
+    default:
+      if constexpr (T < 1024) {
+        switch (j) {
+          case 6: level_step<6, T>(v, chunk, m, lds, nt); break;
+          case 7: level_step<7, T>(v, chunk, m, lds, nt); break;
+          case 8: level_step<8, T>(v, chunk, m, lds, nt); break;
+          case 9: level_step<9, T>(v, chunk, m, lds, nt); break;
+          case 10: level_step<10, T>(v, chunk, m, lds, nt); break;
+          default: level_step<11, T>(v, chunk, m, lds, nt); break;
+        }
+      }
+      break;
   }
 }
 
@@ -271,6 +286,155 @@ __global__ __launch_bounds__(T) void k_step1d_solo(const Solo1D a, int64_t sigma
          j > 0 ? a.R[j - 1] : 1, a.n, a.M, a.bc, a.fe, a.stages, a.wrap, a.B, a.H, a.dt,
          a.ce, a.nu_h2, a.divisor};
   dispatch_level<T>(j, v, chunk, m, lds, a.nt_store != 0);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fused integration: one workgroup owns one instance for a range of pipeline steps.  The P levels
+// run concurrently in P thread groups of G threads (whole waves); every group does the
+// same PCR stages, so all groups share the workgroup barriers.  Each group solves its level's
+// whole cycle in its own LDS region (the "wrap" tiling of the per-step kernel, with the same
+// operations per row, so results are bitwise those of the per-step kernel).  The level rings
+// stay in global memory, hot in this CU's caches; a barrier after the stores makes a step's
+// values visible to the next step's loads.
+// ---------------------------------------------------------------------------------------------
+template <int J>
+__device__ __forceinline__ void fused_rhs(const View& L, int64_t m, double* d, int lt, int G) {
+  Geo g;
+  Step<J> S;
+  make_step<J>(L, m, g, S);
+  const int ms = g.per ? g.n : g.n + 2;
+  for (int l = lt; l < ms; l += G) d[l] = rhs_ext<J>(g, S, l);
+}
+
+template <int MJ>
+__device__ __forceinline__ void fused_rhs_any(int j, const View& v, int64_t m, double* d, int lt,
+                                              int G) {
+  // levels up to MJ are instantiated (the host sends orders up to MJ + 1)
+  switch (j) {
+    case 0: fused_rhs<0>(v, m, d, lt, G); break;
+    case 1: if constexpr (MJ >= 1) fused_rhs<1>(v, m, d, lt, G); break;
+    case 2: if constexpr (MJ >= 2) fused_rhs<2>(v, m, d, lt, G); break;
+    case 3: if constexpr (MJ >= 3) fused_rhs<3>(v, m, d, lt, G); break;
+    case 4: if constexpr (MJ >= 4) fused_rhs<4>(v, m, d, lt, G); break;
+    default: if constexpr (MJ >= 5) fused_rhs<5>(v, m, d, lt, G); break;
+  }
+}
+
+// DB: two LDS buffers per level (one barrier per stage); otherwise one buffer with the new
+// values staged in registers (RPT rows per thread at most).
+template <bool DB, int RPT, int MJ>
+__device__ __forceinline__ void fused_body(const Fused1D& F) {
+  extern __shared__ double lds[];
+  const int P = F.P;
+  const int G = F.group;                     // threads per level group
+  const int j = threadIdx.x / G;             // this thread's level (j >= P: idle)
+  const int lt = threadIdx.x - j * G;
+  const bool mine = j < P;
+  const int n = F.n, M = F.M;
+  const bool per = F.bc == RIDC_BC_PERIODIC;
+  const int ms = per ? n : n + 2;
+  const int l0 = per ? 0 : 1, l1 = per ? n : n + 1;
+  double* d0 = lds + (mine ? j : 0) * (DB ? 2 : 1) * ms;
+  double* d1 = DB ? d0 + ms : d0;
+  View v{};
+  if (mine) {
+    v = View{F.ring[j], j > 0 ? F.ring[j - 1] : nullptr, F.W[j], F.gamma, F.shift, F.R[j],
+             j > 0 ? F.R[j - 1] : 1, n, M, F.bc, F.fe, F.stages, 1, 0, 0, F.dt, F.ce, F.nu_h2,
+             F.divisor};
+    // Dirichlet ghost rows (0 and n+1) must read zero in both buffers whatever their roles: a
+    // level waiting for its start-up swaps the buffers without writing them
+    for (int l = lt; l < ms; l += G) {
+      d0[l] = 0.0;
+      if (DB) d1[l] = 0.0;
+    }
+  }
+  const int stages = F.stages;
+  for (int64_t sigma = F.sigma_first + 1; sigma <= F.sigma_last; ++sigma) {
+    const int64_t m = sigma - F.sigma0 - (int64_t)j * (j + 1) / 2;
+    const bool act = mine && m >= 1 && m <= F.nt;
+    if (act) fused_rhs_any<MJ>(j, v, m, d0, lt, G);
+    __syncthreads();
+    for (int k = 0; k < stages; ++k) {
+      const int sh = F.shift[k];
+      const double g = F.gamma[k];
+      if constexpr (DB) {
+        if (act) {
+          for (int l = l0 + lt; l < l1; l += G) {
+            int ia = l - sh;
+            if (ia < 0) ia += M;
+            int ib = l + sh;
+            if (ib >= M) ib -= M;
+            double da, db;
+            if (per) {
+              da = d0[ia];
+              db = d0[ib];
+            } else {
+              da = ia <= n + 1 ? d0[ia] : -d0[M - ia];
+              db = ib <= n + 1 ? d0[ib] : -d0[M - ib];
+            }
+            d1[l] = d0[l] - g * (da + db);
+          }
+        }
+        __syncthreads();
+        double* t = d0;
+        d0 = d1;
+        d1 = t;
+      } else {
+        double nv[RPT];
+        if (act) {
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) {
+            const int l = l0 + lt + r * G;
+            if (l < l1) {
+              int ia = l - sh;
+              if (ia < 0) ia += M;
+              int ib = l + sh;
+              if (ib >= M) ib -= M;
+              double da, db;
+              if (per) {
+                da = d0[ia];
+                db = d0[ib];
+              } else {
+                da = ia <= n + 1 ? d0[ia] : -d0[M - ia];
+                db = ib <= n + 1 ? d0[ib] : -d0[M - ib];
+              }
+              nv[r] = d0[l] - g * (da + db);
+            }
+          }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) {
+            const int l = l0 + lt + r * G;
+            if (l < l1) d0[l] = nv[r];
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (act) {
+      double* out = F.ring[j] + (m % F.R[j]) * (int64_t)n;
+      for (int l = l0 + lt; l < l1; l += G) out[per ? l : l - 1] = d0[l] / F.divisor;
+    }
+    __syncthreads();                         // this step's values before the next step reads
+  }
+}
+
+// Double-buffered variants run 1024 threads; single-buffered ones 512 (room for the staged
+// rows in registers).
+template <bool DB>
+constexpr int fused_threads() { return DB ? 1024 : 512; }
+
+template <bool DB, int RPT, int MJ>
+__global__ __launch_bounds__(fused_threads<DB>()) void k_fused1d(const Fused1D* __restrict__ items) {
+  fused_body<DB, RPT, MJ>(items[blockIdx.x]);
+}
+
+// One instance, descriptor in the kernel arguments.
+template <bool DB, int RPT, int MJ>
+__global__ __launch_bounds__(fused_threads<DB>()) void k_fused1d_one(const Fused1D F) {
+  fused_body<DB, RPT, MJ>(F);
 }
 
 __global__ void k_nonfinite(const double* __restrict__ x, int64_t count, int* flag) {
@@ -373,6 +537,59 @@ hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, size_t lds_
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+namespace {
+
+template <bool DB, int RPT, int MJ>
+hipError_t fused_launch(const Fused1D* d_items, const Fused1D* one, int count, size_t lds,
+                        hipStream_t stream) {
+  static size_t allowed_tab = 65536, allowed_one = 65536;
+  const void* ftab = reinterpret_cast<const void*>(&k_fused1d<DB, RPT, MJ>);
+  const void* fone = reinterpret_cast<const void*>(&k_fused1d_one<DB, RPT, MJ>);
+  if (one) {
+    if (lds > allowed_one) {
+      hipError_t e = hipFuncSetAttribute(fone, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      allowed_one = lds;
+    }
+    hipLaunchKernelGGL((k_fused1d_one<DB, RPT, MJ>), dim3(1), dim3(fused_threads<DB>()), lds,
+                       stream, *one);
+  } else {
+    if (lds > allowed_tab) {
+      hipError_t e = hipFuncSetAttribute(ftab, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      allowed_tab = lds;
+    }
+    hipLaunchKernelGGL((k_fused1d<DB, RPT, MJ>), dim3(count), dim3(fused_threads<DB>()), lds,
+                       stream, d_items);
+  }
+  return hipGetLastError();
+}
+
+template <int MJ>
+hipError_t fused_launch_mj(const Fused1D* d_items, const Fused1D* one, int count, bool db, int rpt,
+                           size_t lds, hipStream_t stream) {
+  if (db) return fused_launch<true, 1, MJ>(d_items, one, count, lds, stream);
+  switch (rpt) {
+    case 4: return fused_launch<false, 4, MJ>(d_items, one, count, lds, stream);
+    case 8: return fused_launch<false, 8, MJ>(d_items, one, count, lds, stream);
+    case 16: return fused_launch<false, 16, MJ>(d_items, one, count, lds, stream);
+    case 32: return fused_launch<false, 32, MJ>(d_items, one, count, lds, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fused_1d(const Fused1D* d_items, const Fused1D* one, int count, int max_order,
+                           bool double_buffer, int rpt, size_t lds_bytes, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  if (max_order <= 4)
+    return fused_launch_mj<3>(d_items, one, count, double_buffer, rpt, lds_bytes, stream);
+  if (max_order <= kMaxJ1024 + 1)
+    return fused_launch_mj<kMaxJ1024>(d_items, one, count, double_buffer, rpt, lds_bytes, stream);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_nonfinite_check(const double* x, int64_t count, int* flag, hipStream_t stream) {

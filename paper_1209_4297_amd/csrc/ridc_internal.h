@@ -97,6 +97,20 @@ struct Solo1D {
   double dt, ce, nu_h2, divisor;
 };
 
+// One instance integrated by the fused kernel (one workgroup): pipeline steps
+// sigma_first+1 .. sigma_last of its own schedule (own step = sigma - sigma0).
+constexpr int kMaxJ1024 = 5;   // highest level index instantiated in 1024-thread kernels
+struct Fused1D {
+  double* ring[kMaxOrder];
+  const double* W[kMaxOrder];
+  const double* gamma;
+  const int32_t* shift;
+  int32_t R[kMaxOrder];
+  int64_t nt, sigma0, sigma_first, sigma_last;
+  int32_t P, group, n, M, bc, fe, stages, pad;
+  double dt, ce, nu_h2, divisor;
+};
+
 struct Blk1D {
   int32_t item;
   int32_t chunk;
@@ -114,6 +128,15 @@ hipError_t launch_1d_step(const Lvl1D* d_items, const Blk1D* d_blocks, int nbloc
 // covers level b / nchunks, chunk b % nchunks.
 hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, size_t lds_bytes,
                           int64_t sigma, hipStream_t stream);
+
+// Launch the fused integration of `count` instances (one workgroup each).  double_buffer: two
+// LDS buffers per level and 1024 threads; else one buffer, 512 threads and at most rpt rows per
+// thread (4, 8, 16 or 32) staged in registers.  The level groups have Fused1D::group threads.
+// `one` (nullable): a single instance whose descriptor goes in the kernel arguments (count 1);
+// otherwise d_items holds `count` device descriptors.
+// max_order: the largest order among the instances (at most kMaxJ1024 + 1).
+hipError_t launch_fused_1d(const Fused1D* d_items, const Fused1D* one, int count, int max_order,
+                           bool double_buffer, int rpt, size_t lds_bytes, hipStream_t stream);
 
 // Set *flag to 1 if any of x[0..count) is not finite.
 hipError_t launch_nonfinite_check(const double* x, int64_t count, int* flag, hipStream_t stream);

@@ -227,3 +227,27 @@ def test_tilings_are_bitwise_identical(env):
     _say(f"autotuned: threads={t} rows={r} flags={f}")
     np.testing.assert_array_equal(s.integrate(x0, prob["nt"]).cpu().numpy(), outs[0])
     s.close()
+
+
+@pytest.mark.parametrize("bc,n,order,nt", [("periodic", 1000, 4, 50), ("dirichlet", 999, 4, 40),
+                                           ("periodic", 4096, 4, 30), ("dirichlet", 3000, 3, 30),
+                                           ("periodic", 128, 1, 20), ("dirichlet", 64, 6, 25),
+                                           ("periodic", 2048, 2, 40)])
+def test_fused_integration_equals_per_step_kernel(env, monkeypatch, bc, n, order, nt):
+    """Systems that fit one CU run their whole integration in one workgroup; the result is
+    bitwise that of one launch per pipeline step."""
+    torch, ridc = env
+    length = 2 * math.pi if bc == "periodic" else 1.0
+    x = workloads.grid_points(bc, n, length)
+    u0 = np.sin(x) + 0.25 * np.cos(5 * x) if bc == "periodic" else x * (length - x) * 4
+    prob = dict(dim=1, bc=bc, n=n, length=length, fe="advect" if bc == "periodic" else "logistic",
+                a=0.6, nu=2e-3, T=0.05, nt=nt, order=order)
+    _say(f"case: fused vs per-step {bc} n={n} P={order} nt={nt}")
+    fused, lv_f = run_gpu(env, prob, u0)
+    monkeypatch.setenv("RIDC_FUSED", "0")
+    step, lv_s = run_gpu(env, prob, u0)
+    np.testing.assert_array_equal(fused, step)
+    np.testing.assert_array_equal(lv_f, lv_s)
+    p = Problem(dim=1, bc=bc, n=n, length=length, fe=prob["fe"], a=0.6, nu=2e-3, dt=0.05 / nt)
+    ref = ridc_pipelined(p, u0, nt, order)[-1]
+    assert rel_l2(fused, ref) <= TOL

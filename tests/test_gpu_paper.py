@@ -34,7 +34,7 @@ def test_paper_advection_diffusion(env, segments):
     assert abs(out.mean() - 2.0) < 1e-12
 
 
-@pytest.mark.parametrize("nt", [200, 1000])
+@pytest.mark.parametrize("nt", [1000, 2000])
 def test_paper_burgers(env, nt):
     torch, ridc = env
     prob, u0 = workloads.config_paper_burgers(nt=nt)       # N=999 interior, eps=1e-3, T=1
@@ -51,3 +51,15 @@ def test_paper_burgers(env, nt):
         print(f"  level {j}: rel L2 {err:.3e}", flush=True)
         assert err <= 1e-12
     np.testing.assert_array_equal(out, lvs[-1])
+
+
+def test_paper_burgers_beyond_cfl_is_reported(env):
+    """dt = 5e-3 with dx = 1e-3 puts the explicit flux far beyond its stability limit: the
+    integration blows up, and the library reports it instead of returning garbage."""
+    torch, ridc = env
+    prob, u0 = workloads.config_paper_burgers(nt=200)
+    s = ridc.Ridc(prob)
+    with pytest.raises(ridc.RidcError) as ei:
+        s.integrate(torch.tensor(u0, dtype=torch.float64, device="cuda"), 200)
+    assert ei.value.code == ridc.RIDC_E_NONFINITE
+    s.close()
