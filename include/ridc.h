@@ -175,7 +175,9 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32
 
 /* Force a 1D tiling: threads in {64,128,256,512,1024}; rows = 0 for the whole cycle in one
  * workgroup, else chunks of `rows` rows (allowed when the PCR coupling vanishes within a halo
- * shorter than the system); flags bit 0 = write level values with nontemporal stores.
+ * shorter than the system); flags bit 0 = write level values with nontemporal stores; flags
+ * bit 1 = one workgroup of `threads` (512 or 1024, rows 0) runs every level and many pipeline
+ * steps in one launch (needs the levels' cycles to fit one CU's LDS, order <= 6).
  * Errors: RIDC_E_INVAL if the tiling does not fit.                                            */
 int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags);
 

@@ -63,9 +63,9 @@ struct ridc_handle {
   Solo1D solo{};              // kernel-argument descriptor of a single-instance launch
   int solo_blocks = 0;
   // fused integration (one workgroup per instance) when the levels fit one CU's LDS
-  bool fused = false;
-  bool fused_db = false;
-  int fused_rpt = 0;
+  bool fused = false;          // whole-range workgroup in use
+  bool fused_ok = false;       // the levels fit one CU's LDS
+  int fused_threads = 512;
   size_t fused_lds = 0;
   Fused1D fused_item{};
   Fused1D* d_fused = nullptr;
@@ -144,6 +144,7 @@ struct Tile1D {
   int B = 0;
   int threads = 256;
   int nt_store = 0;   // write new level values with nontemporal stores
+  int fused = 0;      // 0: one launch per pipeline step; 512/1024: whole-range workgroup threads
 };
 
 std::mutex g_tune_mu;
@@ -168,46 +169,31 @@ int64_t halo_rows(const PcrPlan& pcr) {
   return pcr.stages < 30 ? ((int64_t)1 << pcr.stages) - 1 : ((int64_t)1 << 40);
 }
 
-// Fused integration plan: P level groups of G threads (whole waves) in one workgroup, each
-// level's cycle in LDS: two buffers and 1024 threads when they fit, else one buffer, 512
-// threads and the new values staged in registers (at most 32 rows per thread).
+// Fused integration plan: P level groups of G threads (whole waves) in one workgroup of 1024,
+// two LDS buffers per level holding the whole cycle.
 struct FusedPlan {
   bool ok = false, db = false;
   int group = 0, rpt = 0;
   size_t lds = 0;
 };
 
-FusedPlan plan_fused(const ridc_problem* p) {
+FusedPlan plan_fused(const ridc_problem* p, int threads) {
   FusedPlan f;
   if (p->dim != 1 || p->order > kMaxJ1024 + 1) return f;
   const int P = p->order;
   const int64_t ms = p->bc == RIDC_BC_PERIODIC ? p->n : p->n + 2;
-  const int64_t rows = p->n;
   const size_t maxl = (size_t)device_max_lds();
-  // two buffers per level, 1024 threads
-  const int G1 = (1024 / P) / 64 * 64;
-  if ((size_t)P * 2 * ms * sizeof(double) <= maxl && rows <= (int64_t)G1 * 64) {
+  const int G = (threads / P) / 64 * 64;
+  if (G >= 64 && (size_t)P * 2 * ms * sizeof(double) <= maxl) {
     f.ok = f.db = true;
-    f.group = G1;
+    f.group = G;
     f.lds = (size_t)P * 2 * ms * sizeof(double);
-    return f;
   }
-  // one buffer per level, 512 threads, rows staged in registers
-  const int G2 = (512 / P) / 64 * 64;
-  if (G2 < 64 || (size_t)P * ms * sizeof(double) > maxl) return f;
-  const int64_t need = (rows + G2 - 1) / G2;
-  for (int r : {4, 8, 16, 32})
-    if (need <= r) {
-      f.ok = true;
-      f.group = G2;
-      f.rpt = r;
-      f.lds = (size_t)P * ms * sizeof(double);
-      return f;
-    }
   return f;
 }
 
 bool tile_fits(const ridc_problem* p, const PcrPlan& pcr, const Tile1D& t) {
+  if (t.fused) return (t.fused == 512 || t.fused == 1024) && plan_fused(p, t.fused).ok;
   const int64_t M = p->bc == RIDC_BC_PERIODIC ? p->n : 2 * p->n + 2;
   const int64_t ms = p->bc == RIDC_BC_PERIODIC ? p->n : p->n + 2;
   if (t.threads != 64 && t.threads != 128 && t.threads != 256 && t.threads != 512 &&
@@ -228,6 +214,7 @@ int choose_tile_1d(const ridc_problem* p, const PcrPlan& pcr, Tile1D* out) {
   }
   const int64_t H = halo_rows(pcr);
   // default: chunks of 1024 rows when the system is long and the halo is small against them
+  // (the whole-range workgroup is left to measurement: ridc_autotune, ridc_set_tile)
   Tile1D chunk{0, 1024, 256};
   if (p->n >= 2048 && H <= 512 && tile_fits(p, pcr, chunk)) {
     *out = chunk;
@@ -454,8 +441,7 @@ int launch_fused_steps(ridc_handle* h, int64_t first, int64_t last) {
   F.sigma0 = 0;
   F.sigma_first = first - 1;
   F.sigma_last = last;
-  RIDC_HIP_TRY(launch_fused_1d(nullptr, &F, 1, h->P, h->fused_db, h->fused_rpt, h->fused_lds,
-                               h->stream));
+  RIDC_HIP_TRY(launch_fused_1d(nullptr, &F, 1, h->P, h->fused_threads, h->fused_lds, h->stream));
   return RIDC_OK;
 }
 
@@ -479,6 +465,20 @@ int check_handles(ridc_handle* const* hs, int32_t count) {
 
 int apply_tile_1d(ridc_handle* h, const Tile1D& t) {
   if (!tile_fits(&h->p, h->pcr, t)) return fail(RIDC_E_INVAL, "tile does not fit this system");
+  if (t.fused) {
+    const FusedPlan fp = plan_fused(&h->p, t.fused);
+    h->fused = true;
+    h->fused_threads = t.fused;
+    h->fused_lds = fp.lds;
+    h->fused_item.group = fp.group;
+    if (h->gexec) {
+      (void)hipGraphExecDestroy(h->gexec);
+      h->gexec = nullptr;
+    }
+    h->graph_nt = -1;
+    return RIDC_OK;
+  }
+  h->fused = false;
   const size_t nchunks = t.wrap ? 1 : (size_t)((h->p.n + t.B - 1) / t.B);
   if (nchunks * h->P > h->blocks_cap) return fail(RIDC_E_INVAL, "tile finer than the minimum chunk");
   build_items_1d(h, t);
@@ -501,6 +501,25 @@ int apply_tile_1d(ridc_handle* h, const Tile1D& t) {
 int time_tile_1d(ridc_handle* h, const Tile1D& t, int reps, float* ms) {
   int rc = apply_tile_1d(h, t);
   if (rc != RIDC_OK) return rc;
+  if (t.fused) {
+    const int64_t saved = h->nt;
+    h->nt = (int64_t)1 << 40;
+    const int64_t first = (int64_t)h->P * (h->P - 1) / 2 + 1;
+    hipEvent_t a, b;
+    RIDC_HIP_TRY(hipEventCreate(&a));
+    RIDC_HIP_TRY(hipEventCreate(&b));
+    rc = launch_fused_steps(h, first, first + 4);                // warm-up
+    if (rc == RIDC_OK) {
+      (void)hipEventRecord(a, h->stream);
+      rc = launch_fused_steps(h, first + 5, first + 4 + reps);
+      (void)hipEventRecord(b, h->stream);
+    }
+    if (rc == RIDC_OK && hipEventSynchronize(b) == hipSuccess) (void)hipEventElapsedTime(ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    h->nt = saved;
+    return rc;
+  }
   for (auto& it : h->proto) it.nt = (int64_t)1 << 40;
   h->solo.nt = (int64_t)1 << 40;
   RIDC_HIP_TRY(hipMemcpyAsync(h->d_items, h->proto.data(), sizeof(Lvl1D) * h->proto.size(),
@@ -634,10 +653,10 @@ int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out) {
     cur += L.blocks;
     h->blocks_cap = (size_t)L.nblocks;
     build_items_1d(h, tile);
-    const FusedPlan fp = plan_fused(p);
-    h->fused = fp.ok && env_flag("RIDC_FUSED", true);
-    h->fused_db = fp.db;
-    h->fused_rpt = fp.rpt;
+    h->fused_ok = plan_fused(p, 512).ok;
+    h->fused = tile.fused != 0;
+    h->fused_threads = tile.fused ? tile.fused : 512;
+    const FusedPlan fp = plan_fused(p, h->fused_threads);
     h->fused_lds = fp.lds;
     {
       Fused1D& F = h->fused_item;
@@ -735,10 +754,11 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
     if (hs[i]->total - hs[i]->sigma <= 0) continue;
     (hs[i]->p.dim == 1 ? h1 : h2).push_back(hs[i]);
   }
-  // fused-eligible 1D handles: one workgroup each, every requested step in one launch, with the
-  // variant (two LDS buffers, or one buffer and staged rows) that fits all of them
+  // fused-eligible 1D handles: one workgroup each, every requested step in one launch
   {
     std::vector<ridc_handle*> hf, hs;
+    // batches keep the GPU busy with one launch per step (measured faster than whole-range
+    // workgroups); a handle tuned to the whole-range workgroup keeps it
     for (auto* h : h1) (h->fused ? hf : hs).push_back(h);
     h1.swap(hs);
     if (!hf.empty()) {
@@ -746,41 +766,26 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
       if (rc != RIDC_OK) return rc;
       rc = arena_reserve_fused(hf.size());
       if (rc != RIDC_OK) return rc;
-      bool db = true;
       int maxP = 1;
-      for (auto* h : hf) {
-        db = db && h->fused_db;
-        maxP = std::max(maxP, h->P);
-      }
-      int rpt = 0;
       size_t lds = 0;
       for (size_t i = 0; i < hf.size(); ++i) {
         ridc_handle* h = hf[i];
-        const int64_t ms = h->p.bc == RIDC_BC_PERIODIC ? h->p.n : h->p.n + 2;
+        maxP = std::max(maxP, h->P);
+        const FusedPlan fp = plan_fused(&h->p, 512);
+        lds = std::max(lds, fp.lds);
         Fused1D F = h->fused_item;
-        if (db) {
-          F.group = (1024 / h->P) / 64 * 64;
-          lds = std::max(lds, (size_t)h->P * 2 * ms * sizeof(double));
-        } else {
-          F.group = (512 / h->P) / 64 * 64;
-          const int64_t need = (h->p.n + F.group - 1) / F.group;
-          int r = 4;
-          while (r < need) r *= 2;
-          rpt = std::max(rpt, r);
-          lds = std::max(lds, (size_t)h->P * ms * sizeof(double));
-        }
+        F.group = fp.group;
         F.nt = h->nt;
         F.sigma0 = 0;
         F.sigma_first = h->sigma;
         F.sigma_last = std::min(h->total, h->sigma + max_steps);
         g_arena.h_fused[i] = F;
       }
-      if (!db && rpt > 32) return fail(RIDC_E_UNSUPPORTED, "fused batch rows per thread");
       RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_fused, g_arena.h_fused, sizeof(Fused1D) * hf.size(),
                                   hipMemcpyHostToDevice, stream));
       RIDC_HIP_TRY(hipEventRecord(g_arena.done, stream));
       g_arena.pending = true;
-      RIDC_HIP_TRY(launch_fused_1d(g_arena.d_fused, nullptr, (int)hf.size(), maxP, db, rpt, lds,
+      RIDC_HIP_TRY(launch_fused_1d(g_arena.d_fused, nullptr, (int)hf.size(), maxP, 512, lds,
                                    stream));
       for (auto* h : hf) h->sigma = std::min(h->total, h->sigma + max_steps);
     }
@@ -963,8 +968,12 @@ int ridc_integrate_batch(ridc_handle* const* hs, int32_t count, const double* co
 int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags) {
   if (!h) return fail(RIDC_E_INVAL, "NULL handle");
   if (h->p.dim != 1) return fail(RIDC_E_UNSUPPORTED, "tiles are chosen per system in 1D only");
-  if (rows < 0 || (flags & ~1)) return fail(RIDC_E_INVAL, "bad rows or flags");
-  Tile1D t{rows == 0 ? 1 : 0, rows, threads, flags & 1};
+  if (rows < 0 || (flags & ~3)) return fail(RIDC_E_INVAL, "bad rows or flags");
+  if (flags & 2) {
+    if (rows != 0) return fail(RIDC_E_INVAL, "the whole-range workgroup holds whole cycles");
+    return apply_tile_1d(h, Tile1D{1, 0, 256, 0, threads});
+  }
+  Tile1D t{rows == 0 ? 1 : 0, rows, threads, flags & 1, 0};
   return apply_tile_1d(h, t);
 }
 
@@ -983,6 +992,7 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32
   for (int j = 0; j < h->P; ++j) slots += h->R[j];
   RIDC_HIP_TRY(hipMemsetAsync(h->ring[0], 0, sizeof(double) * (size_t)(slots * h->npts), h->stream));
   std::vector<Tile1D> cands;
+  for (int ft : {512, 1024}) cands.push_back(Tile1D{1, 0, 256, 0, ft});
   for (int nts : {0, 1})
     for (int T : {256, 512, 1024}) {
       cands.push_back(Tile1D{1, 0, T, nts});
@@ -1015,9 +1025,9 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32
   h->sigma = h->total = 0;
   int rc = apply_tile_1d(h, best);
   if (rc != RIDC_OK) return rc;
-  if (threads_out) *threads_out = best.threads;
+  if (threads_out) *threads_out = best.fused ? best.fused : best.threads;
   if (rows_out) *rows_out = best.wrap ? 0 : best.B;
-  if (flags_out) *flags_out = best.nt_store;
+  if (flags_out) *flags_out = best.nt_store | (best.fused ? 2 : 0);
   return RIDC_OK;
 }
 

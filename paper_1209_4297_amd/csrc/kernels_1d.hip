@@ -297,13 +297,30 @@ __global__ __launch_bounds__(T) void k_step1d_solo(const Solo1D a, int64_t sigma
 // stay in global memory, hot in this CU's caches; a barrier after the stores makes a step's
 // values visible to the next step's loads.
 // ---------------------------------------------------------------------------------------------
+// Thread lt of a level group owns rows l0 + lt + r G, r < RPT (RHS rows: lt + r G of [0, ms)).
+// Every phase first gathers what all of its rows need into registers, so the loads of a phase
+// are in flight together, then computes, then writes.
 template <int J>
 __device__ __forceinline__ void fused_rhs(const View& L, int64_t m, double* d, int lt, int G) {
   Geo g;
   Step<J> S;
   make_step<J>(L, m, g, S);
   const int ms = g.per ? g.n : g.n + 2;
-  for (int l = lt; l < ms; l += G) d[l] = rhs_ext<J>(g, S, l);
+  constexpr int RB = 1;                       // rows whose loads are in flight together
+#pragma unroll 1
+  for (int base = lt; base < ms; base += RB * G) {
+    double v[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int l = base + r * G;
+      v[r] = l < ms ? rhs_ext<J>(g, S, l) : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int l = base + r * G;
+      if (l < ms) d[l] = v[r];
+    }
+  }
 }
 
 template <int MJ>
@@ -320,13 +337,12 @@ __device__ __forceinline__ void fused_rhs_any(int j, const View& v, int64_t m, d
   }
 }
 
-// DB: two LDS buffers per level (one barrier per stage); otherwise one buffer with the new
-// values staged in registers (RPT rows per thread at most).
-template <bool DB, int RPT, int MJ>
+// Two LDS buffers per level, one barrier per stage.
+template <int MJ>
 __device__ __forceinline__ void fused_body(const Fused1D& F) {
   extern __shared__ double lds[];
   const int P = F.P;
-  const int G = F.group;                     // threads per level group
+  const int G = F.group;                     // threads per level group (blockDim.x / P, waves)
   const int j = threadIdx.x / G;             // this thread's level (j >= P: idle)
   const int lt = threadIdx.x - j * G;
   const bool mine = j < P;
@@ -334,8 +350,8 @@ __device__ __forceinline__ void fused_body(const Fused1D& F) {
   const bool per = F.bc == RIDC_BC_PERIODIC;
   const int ms = per ? n : n + 2;
   const int l0 = per ? 0 : 1, l1 = per ? n : n + 1;
-  double* d0 = lds + (mine ? j : 0) * (DB ? 2 : 1) * ms;
-  double* d1 = DB ? d0 + ms : d0;
+  double* d0 = lds + (mine ? j : 0) * 2 * ms;
+  double* d1 = d0 + ms;
   View v{};
   if (mine) {
     v = View{F.ring[j], j > 0 ? F.ring[j - 1] : nullptr, F.W[j], F.gamma, F.shift, F.R[j],
@@ -345,7 +361,7 @@ __device__ __forceinline__ void fused_body(const Fused1D& F) {
     // level waiting for its start-up swaps the buffers without writing them
     for (int l = lt; l < ms; l += G) {
       d0[l] = 0.0;
-      if (DB) d1[l] = 0.0;
+      d1[l] = 0.0;
     }
   }
   const int stages = F.stages;
@@ -357,61 +373,41 @@ __device__ __forceinline__ void fused_body(const Fused1D& F) {
     for (int k = 0; k < stages; ++k) {
       const int sh = F.shift[k];
       const double g = F.gamma[k];
-      if constexpr (DB) {
-        if (act) {
-          for (int l = l0 + lt; l < l1; l += G) {
-            int ia = l - sh;
-            if (ia < 0) ia += M;
-            int ib = l + sh;
-            if (ib >= M) ib -= M;
-            double da, db;
-            if (per) {
-              da = d0[ia];
-              db = d0[ib];
-            } else {
-              da = ia <= n + 1 ? d0[ia] : -d0[M - ia];
-              db = ib <= n + 1 ? d0[ib] : -d0[M - ib];
-            }
-            d1[l] = d0[l] - g * (da + db);
-          }
-        }
-        __syncthreads();
-        double* t = d0;
-        d0 = d1;
-        d1 = t;
-      } else {
-        double nv[RPT];
-        if (act) {
+      if (act) {
+        constexpr int RB = 4;                 // rows gathered together
+#pragma unroll 1
+        for (int base = l0 + lt; base < l1; base += RB * G) {
+          double c[RB], a[RB], b[RB];
 #pragma unroll
-          for (int r = 0; r < RPT; ++r) {
-            const int l = l0 + lt + r * G;
+          for (int r = 0; r < RB; ++r) {
+            const int l = base + r * G;
+            c[r] = a[r] = b[r] = 0.0;
             if (l < l1) {
               int ia = l - sh;
               if (ia < 0) ia += M;
               int ib = l + sh;
               if (ib >= M) ib -= M;
-              double da, db;
+              c[r] = d0[l];
               if (per) {
-                da = d0[ia];
-                db = d0[ib];
+                a[r] = d0[ia];
+                b[r] = d0[ib];
               } else {
-                da = ia <= n + 1 ? d0[ia] : -d0[M - ia];
-                db = ib <= n + 1 ? d0[ib] : -d0[M - ib];
+                a[r] = ia <= n + 1 ? d0[ia] : -d0[M - ia];
+                b[r] = ib <= n + 1 ? d0[ib] : -d0[M - ib];
               }
-              nv[r] = d0[l] - g * (da + db);
             }
           }
-        }
-        __syncthreads();
-        if (act) {
 #pragma unroll
-          for (int r = 0; r < RPT; ++r) {
-            const int l = l0 + lt + r * G;
-            if (l < l1) d0[l] = nv[r];
+          for (int r = 0; r < RB; ++r) {
+            const int l = base + r * G;
+            if (l < l1) d1[l] = c[r] - g * (a[r] + b[r]);
           }
         }
-        __syncthreads();
       }
+      __syncthreads();
+      double* t = d0;
+      d0 = d1;
+      d1 = t;
     }
     if (act) {
       double* out = F.ring[j] + (m % F.R[j]) * (int64_t)n;
@@ -421,21 +417,17 @@ __device__ __forceinline__ void fused_body(const Fused1D& F) {
   }
 }
 
-// Double-buffered variants run 1024 threads; single-buffered ones 512 (room for the staged
-// rows in registers).
-template <bool DB>
-constexpr int fused_threads() { return DB ? 1024 : 512; }
-
-template <bool DB, int RPT, int MJ>
-__global__ __launch_bounds__(fused_threads<DB>()) void k_fused1d(const Fused1D* __restrict__ items) {
-  fused_body<DB, RPT, MJ>(items[blockIdx.x]);
+template <int MJ, int FT>
+__global__ __launch_bounds__(FT) void k_fused1d(const Fused1D* __restrict__ items) {
+  fused_body<MJ>(items[blockIdx.x]);
 }
 
 // One instance, descriptor in the kernel arguments.
-template <bool DB, int RPT, int MJ>
-__global__ __launch_bounds__(fused_threads<DB>()) void k_fused1d_one(const Fused1D F) {
-  fused_body<DB, RPT, MJ>(F);
+template <int MJ, int FT>
+__global__ __launch_bounds__(FT) void k_fused1d_one(const Fused1D F) {
+  fused_body<MJ>(F);
 }
+
 
 __global__ void k_nonfinite(const double* __restrict__ x, int64_t count, int* flag) {
   int bad = 0;
@@ -541,54 +533,44 @@ hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, size_t lds_
 
 namespace {
 
-template <bool DB, int RPT, int MJ>
+template <int MJ, int FT>
 hipError_t fused_launch(const Fused1D* d_items, const Fused1D* one, int count, size_t lds,
                         hipStream_t stream) {
   static size_t allowed_tab = 65536, allowed_one = 65536;
-  const void* ftab = reinterpret_cast<const void*>(&k_fused1d<DB, RPT, MJ>);
-  const void* fone = reinterpret_cast<const void*>(&k_fused1d_one<DB, RPT, MJ>);
   if (one) {
     if (lds > allowed_one) {
-      hipError_t e = hipFuncSetAttribute(fone, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused1d_one<MJ, FT>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       allowed_one = lds;
     }
-    hipLaunchKernelGGL((k_fused1d_one<DB, RPT, MJ>), dim3(1), dim3(fused_threads<DB>()), lds,
-                       stream, *one);
+    hipLaunchKernelGGL((k_fused1d_one<MJ, FT>), dim3(1), dim3(FT), lds, stream, *one);
   } else {
     if (lds > allowed_tab) {
-      hipError_t e = hipFuncSetAttribute(ftab, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused1d<MJ, FT>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       allowed_tab = lds;
     }
-    hipLaunchKernelGGL((k_fused1d<DB, RPT, MJ>), dim3(count), dim3(fused_threads<DB>()), lds,
-                       stream, d_items);
+    hipLaunchKernelGGL((k_fused1d<MJ, FT>), dim3(count), dim3(FT), lds, stream, d_items);
   }
   return hipGetLastError();
-}
-
-template <int MJ>
-hipError_t fused_launch_mj(const Fused1D* d_items, const Fused1D* one, int count, bool db, int rpt,
-                           size_t lds, hipStream_t stream) {
-  if (db) return fused_launch<true, 1, MJ>(d_items, one, count, lds, stream);
-  switch (rpt) {
-    case 4: return fused_launch<false, 4, MJ>(d_items, one, count, lds, stream);
-    case 8: return fused_launch<false, 8, MJ>(d_items, one, count, lds, stream);
-    case 16: return fused_launch<false, 16, MJ>(d_items, one, count, lds, stream);
-    case 32: return fused_launch<false, 32, MJ>(d_items, one, count, lds, stream);
-    default: return hipErrorInvalidValue;
-  }
 }
 
 }  // namespace
 
 hipError_t launch_fused_1d(const Fused1D* d_items, const Fused1D* one, int count, int max_order,
-                           bool double_buffer, int rpt, size_t lds_bytes, hipStream_t stream) {
+                           int threads, size_t lds_bytes, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  if (max_order <= 4)
-    return fused_launch_mj<3>(d_items, one, count, double_buffer, rpt, lds_bytes, stream);
-  if (max_order <= kMaxJ1024 + 1)
-    return fused_launch_mj<kMaxJ1024>(d_items, one, count, double_buffer, rpt, lds_bytes, stream);
+  if (threads == 512) {
+    if (max_order <= 4) return fused_launch<3, 512>(d_items, one, count, lds_bytes, stream);
+    if (max_order <= kMaxJ1024 + 1)
+      return fused_launch<kMaxJ1024, 512>(d_items, one, count, lds_bytes, stream);
+  } else if (threads == 1024) {
+    if (max_order <= 4) return fused_launch<3, 1024>(d_items, one, count, lds_bytes, stream);
+    if (max_order <= kMaxJ1024 + 1)
+      return fused_launch<kMaxJ1024, 1024>(d_items, one, count, lds_bytes, stream);
+  }
   return hipErrorInvalidValue;
 }
 

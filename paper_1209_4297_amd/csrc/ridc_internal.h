@@ -129,14 +129,13 @@ hipError_t launch_1d_step(const Lvl1D* d_items, const Blk1D* d_blocks, int nbloc
 hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, size_t lds_bytes,
                           int64_t sigma, hipStream_t stream);
 
-// Launch the fused integration of `count` instances (one workgroup each).  double_buffer: two
-// LDS buffers per level and 1024 threads; else one buffer, 512 threads and at most rpt rows per
-// thread (4, 8, 16 or 32) staged in registers.  The level groups have Fused1D::group threads.
-// `one` (nullable): a single instance whose descriptor goes in the kernel arguments (count 1);
-// otherwise d_items holds `count` device descriptors.
-// max_order: the largest order among the instances (at most kMaxJ1024 + 1).
+// Launch the fused integration of `count` instances (one workgroup of `threads` = 512 or 1024
+// each, two LDS buffers of n (periodic) or n+2 (Dirichlet) doubles per level, level groups of
+// Fused1D::group = (threads / P) rounded down to whole waves).  `one` (nullable): a single instance whose descriptor goes in the
+// kernel arguments; otherwise d_items holds `count` device descriptors.  max_order: the
+// largest order among the instances (at most kMaxJ1024 + 1).
 hipError_t launch_fused_1d(const Fused1D* d_items, const Fused1D* one, int count, int max_order,
-                           bool double_buffer, int rpt, size_t lds_bytes, hipStream_t stream);
+                           int threads, size_t lds_bytes, hipStream_t stream);
 
 // Set *flag to 1 if any of x[0..count) is not finite.
 hipError_t launch_nonfinite_check(const double* x, int64_t count, int* flag, hipStream_t stream);

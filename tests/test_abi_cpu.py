@@ -89,3 +89,34 @@ def test_footprint(ridc):
     assert 17 * 8192 * 8 <= fp < 17 * 8192 * 8 + 64 * 1024
     bad = dict(prob, n=1)
     assert ridc.footprint_bytes(bad) == 0
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(n=1), -1), (dict(dt=0.0), -1), (dict(dt=float("nan")), -1), (dict(order=0), -1),
+    (dict(order=13), -1), (dict(nu=-1.0), -1), (dict(length=0.0), -1), (dict(dim=3), -1),
+    (dict(bc=7), -1), (dict(fe_kind=9), -1), (dict(prec=5), -1), (dict(reserved=1), -1),
+    (dict(dim=2, bc=0), -2), (dict(dim=2, n=100), -2), (dict(dim=2, fe_kind=1), -2),
+    (dict(dim=1, prec=1), -2),
+])
+def test_create_rejects_bad_problems_before_touching_the_device(ridc, change, code):
+    import ctypes
+    import workloads
+    prob, _ = workloads.config_reacdiff_1d()
+    p = ridc.make_problem(prob)
+    for k, v in change.items():
+        setattr(p, k, v)
+    h = ctypes.c_void_p()
+    rc = ridc.lib().ridc_create(ctypes.byref(p), None, ctypes.byref(h))
+    assert rc == code
+    assert not h.value
+    assert ridc.lib().ridc_last_error()                      # a message for the caller
+    assert ridc.lib().ridc_footprint_bytes(ctypes.byref(p)) == 0
+
+
+def test_null_safety(ridc):
+    lib = ridc.lib()
+    assert lib.ridc_destroy(None) == 0
+    assert lib.ridc_remaining(None) == -1
+    assert lib.ridc_sync(None) == ridc.RIDC_E_INVAL
+    assert lib.ridc_read(None, None, None) == ridc.RIDC_E_INVAL
+    assert lib.ridc_advance(None, 0, 5) == 0

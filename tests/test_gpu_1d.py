@@ -31,11 +31,13 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def run_gpu(env, prob, u0, nt=None, levels=True, prec="fp64"):
+def run_gpu(env, prob, u0, nt=None, levels=True, prec="fp64", tile=None):
     torch, ridc = env
     nt = prob["nt"] if nt is None else nt
     dt = prob["T"] / prob["nt"]
     s = ridc.Ridc(prob, dt=dt, prec=prec)
+    if tile is not None:
+        s.set_tile(*tile)
     x0 = torch.tensor(np.asarray(u0), dtype=torch.float64, device="cuda").reshape(-1)
     uT = torch.empty_like(x0)
     lv = torch.empty(prob["order"] * x0.numel(), dtype=torch.float64, device="cuda") if levels else None
@@ -207,12 +209,12 @@ def test_state_errors(env):
 
 def test_tilings_are_bitwise_identical(env):
     torch, ridc = env
-    prob, u0 = workloads.config_reacdiff_1d(n=4096, nt=120, T=0.06)
+    prob, u0 = workloads.config_reacdiff_1d(n=2048, nt=120, T=0.06)
     x0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
     s = ridc.Ridc(prob)
     outs = []
     tiles = [(256, 0, 0), (1024, 0, 1), (256, 1024, 0), (512, 512, 1), (128, 2048, 0),
-             (1024, 256, 1)]
+             (1024, 256, 1), (512, 0, 2), (1024, 0, 2)]
     for threads, rows, flags in tiles:
         try:
             s.set_tile(threads, rows, flags)
@@ -220,7 +222,7 @@ def test_tilings_are_bitwise_identical(env):
             continue
         _say(f"tile threads={threads} rows={rows} flags={flags}")
         outs.append(s.integrate(x0, prob["nt"]).cpu().numpy())
-    assert len(outs) >= 4
+    assert len(outs) >= 6
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
     t, r, f = s.autotune()
@@ -230,10 +232,10 @@ def test_tilings_are_bitwise_identical(env):
 
 
 @pytest.mark.parametrize("bc,n,order,nt", [("periodic", 1000, 4, 50), ("dirichlet", 999, 4, 40),
-                                           ("periodic", 4096, 4, 30), ("dirichlet", 3000, 3, 30),
+                                           ("periodic", 2048, 4, 30), ("dirichlet", 3000, 3, 30),
                                            ("periodic", 128, 1, 20), ("dirichlet", 64, 6, 25),
-                                           ("periodic", 2048, 2, 40)])
-def test_fused_integration_equals_per_step_kernel(env, monkeypatch, bc, n, order, nt):
+                                           ("periodic", 4096, 2, 40)])
+def test_fused_integration_equals_per_step_kernel(env, bc, n, order, nt):
     """Systems that fit one CU run their whole integration in one workgroup; the result is
     bitwise that of one launch per pipeline step."""
     torch, ridc = env
@@ -243,9 +245,10 @@ def test_fused_integration_equals_per_step_kernel(env, monkeypatch, bc, n, order
     prob = dict(dim=1, bc=bc, n=n, length=length, fe="advect" if bc == "periodic" else "logistic",
                 a=0.6, nu=2e-3, T=0.05, nt=nt, order=order)
     _say(f"case: fused vs per-step {bc} n={n} P={order} nt={nt}")
-    fused, lv_f = run_gpu(env, prob, u0)
-    monkeypatch.setenv("RIDC_FUSED", "0")
     step, lv_s = run_gpu(env, prob, u0)
+    fused, lv_f = run_gpu(env, prob, u0, tile=(512, 0, 2))
+    fused2, _ = run_gpu(env, prob, u0, tile=(1024, 0, 2))
+    np.testing.assert_array_equal(fused2, step)
     np.testing.assert_array_equal(fused, step)
     np.testing.assert_array_equal(lv_f, lv_s)
     p = Problem(dim=1, bc=bc, n=n, length=length, fe=prob["fe"], a=0.6, nu=2e-3, dt=0.05 / nt)
