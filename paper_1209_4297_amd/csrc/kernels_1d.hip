@@ -28,6 +28,12 @@ namespace ridc {
 
 namespace {
 
+// One PCR update of a row: c - g (a + b), with one rounding of the product-sum (every path
+// uses this so that all tilings give the same bits).
+__device__ __forceinline__ double pcr_upd(double c, double a, double b, double g) {
+  return __builtin_fma(-g, a + b, c);
+}
+
 // f_E at one point from its neighbours; ce is explicit_coeff(fe, a, h).
 __device__ __forceinline__ double fe_eval(int fe, double ce, double um, double u0, double up) {
   if (fe == RIDC_FE_ADVECT_C2) return -ce * (up - um);
@@ -190,7 +196,7 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
           da = ia <= n + 1 ? d0[ia] : -d0[M - ia];
           db = ib <= n + 1 ? d0[ib] : -d0[M - ib];
         }
-        d1[l] = d0[l] - g * (da + db);
+        d1[l] = pcr_upd(d0[l], da, db, g);
       }
       __syncthreads();
       double* t = d0;
@@ -214,12 +220,33 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
     d0[l] = rhs_ext<J>(G, S, g);
   }
   __syncthreads();
-  for (int k = 0; k < stages; ++k) {
+  // stages in pairs: stage k+1 of row l needs stage k at l and l +- 2s, i.e. the inputs at
+  // l + t s, |t| <= 3 -- one barrier per pair, the same operations as one stage at a time
+  int k = 0;
+  for (; k + 1 < stages; k += 2) {
     const int sh = 1 << k;
-    const int reach = (1 << stages) - (2 << k);       // rows beyond the chunk still needed
+    const int reach = (1 << stages) - (4 << k);       // rows beyond the chunk still needed
+    const int lo = H - reach, hi = H + B + reach;
+    const double ga = gam[k], gb = gam[k + 1];
+    for (int l = lo + threadIdx.x; l < hi; l += T) {
+      const double m3 = d0[l - 3 * sh], m2 = d0[l - 2 * sh], m1 = d0[l - sh], c = d0[l];
+      const double p1 = d0[l + sh], p2 = d0[l + 2 * sh], p3 = d0[l + 3 * sh];
+      const double lm = pcr_upd(m2, m3, m1, ga);      // stage k at l - 2s
+      const double lc = pcr_upd(c, m1, p1, ga);       // stage k at l
+      const double lp = pcr_upd(p2, p1, p3, ga);      // stage k at l + 2s
+      d1[l] = pcr_upd(lc, lm, lp, gb);
+    }
+    __syncthreads();
+    double* t = d0;
+    d0 = d1;
+    d1 = t;
+  }
+  if (k < stages) {
+    const int sh = 1 << k;
+    const int reach = (1 << stages) - (2 << k);
     const int lo = H - reach, hi = H + B + reach;
     const double g = gam[k];
-    for (int l = lo + threadIdx.x; l < hi; l += T) d1[l] = d0[l] - g * (d0[l - sh] + d0[l + sh]);
+    for (int l = lo + threadIdx.x; l < hi; l += T) d1[l] = pcr_upd(d0[l], d0[l - sh], d0[l + sh], g);
     __syncthreads();
     double* t = d0;
     d0 = d1;
@@ -400,7 +427,7 @@ __device__ __forceinline__ void fused_body(const Fused1D& F) {
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
             const int l = base + r * G;
-            if (l < l1) d1[l] = c[r] - g * (a[r] + b[r]);
+            if (l < l1) d1[l] = pcr_upd(c[r], a[r], b[r], g);
           }
         }
       }
