@@ -253,13 +253,7 @@ def bench_batched(args, torch, ridc):
         solvers.append(s)
         u0s.append(torch.tensor(u0, dtype=torch.float64, device="cuda"))
         uTs.append(torch.empty_like(u0s[-1]))
-    tuned = {}
-    for s in solvers:                                   # one measurement per distinct size
-        key = s.npts
-        if key not in tuned:
-            tuned[key] = s.autotune()
-        else:
-            s.set_tile(*tuned[key])
+    batch_tile = ridc.autotune_batch(solvers)           # measured grouped-launch tiling
     nts = [p["nt"] for p, _ in cases]
     for _ in range(warmup):
         ridc.integrate_batch(solvers, u0s, nts, uTs)
@@ -311,7 +305,8 @@ def bench_batched(args, torch, ridc):
             "nu ~ logU(1e-3,1e-1), 8 Fourier modes, RIDC order 4, Nt=1000, T=0.25, FP64")
     return dict(value=total / el, ms=1e3 * el, steps=steps, warmup=warmup, dtype="f64",
                 config={"workload": desc, "instances": len(cases),
-                        "unknowns": sum(p["n"] for p, _ in cases), "nt": nts[0], "order": 4},
+                        "unknowns": sum(p["n"] for p, _ in cases), "nt": nts[0], "order": 4,
+                        "batch_tile": {"threads": batch_tile[0], "rows": batch_tile[1]}},
                 roofline=roof, cpu=cpu, check=check)
 
 

@@ -181,6 +181,24 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32
  * Errors: RIDC_E_INVAL if the tiling does not fit.                                            */
 int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags);
 
+/* Tiling of grouped 1D launches (ridc_advance or ridc_integrate_batch over several 1D handles),
+ * process-wide: `threads` per workgroup (256, 512 or 1024; 1024 falls back to 512 for batches
+ * holding an order above 6) and the most rows a workgroup holds in LDS: rows = 0 puts each
+ * level's whole cycle in one workgroup whenever it fits; rows >= 256 cuts longer cycles into
+ * chunks whose rows plus PCR halos stay within `rows` (systems whose halo is too long for that
+ * keep whole cycles).  Like every tiling it does not change results (section III-E's pipeline
+ * and the solves are computed the same way).  Default: 256 threads, rows 0.
+ * Errors: RIDC_E_INVAL for other values.                                                      */
+int ridc_set_batch_tile(int32_t threads, int32_t rows);
+
+/* Time one grouped launch of the 1D handles among hs[0..count) for every candidate batch tiling
+ * (threads x rows, 20 steady-state steps each, HIP events on the first 1D handle's stream) and
+ * set the fastest as with ridc_set_batch_tile.  The timed steps overwrite the level rings, so
+ * every 1D handle is left unarmed (call ridc_begin again).  threads_out and rows_out (nullable)
+ * receive the choice.  Errors: RIDC_E_INVAL for bad handles, RIDC_E_HIP on launch failures.   */
+int ridc_autotune_batch(ridc_handle* const* hs, int32_t count, int32_t* threads_out,
+                        int32_t* rows_out);
+
 /* Average duration of the dominant kernel per pipeline step, from HIP events on the handle's
  * stream, starting at the handle's next pipeline step (which must have every level active):
  *  - 1D, one launch per step: `reps` back-to-back launches of that step (each recomputes the

@@ -155,6 +155,14 @@ struct TuneKey {
 };
 std::vector<std::pair<TuneKey, Tile1D>> g_tuned;
 
+// Tiling of grouped 1D launches (process-wide, guarded by g_tune_mu): threads per workgroup and
+// the most LDS rows one workgroup holds (0: whole cycles whenever they fit).
+struct BatchTile {
+  int threads = 256;
+  int rows = 0;
+};
+BatchTile g_batch_tile;
+
 bool tuned_tile(int64_t n, int bc, int stages, Tile1D* t) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (auto& e : g_tuned)
@@ -315,7 +323,7 @@ void build_items_1d(ridc_handle* h, const Tile1D& tile) {
   for (auto& it : h->proto) lds = std::max(lds, lds_bytes_1d(it));
   h->lds = lds;
   h->threads = tile.threads;
-  (void)prepare_1d_step(h->threads, h->lds);
+  (void)prepare_1d_step(h->threads, P, h->lds);
   Solo1D& a = h->solo;
   a = Solo1D{};
   for (int j = 0; j < P; ++j) {
@@ -430,7 +438,8 @@ int upload_solo_items(ridc_handle* h) {
 
 int launch_solo_steps_1d(ridc_handle* h, int64_t first, int64_t last) {
   for (int64_t s = first; s <= last; ++s)
-    RIDC_HIP_TRY(launch_1d_solo(h->solo, h->solo_blocks, h->threads, h->lds, s, h->stream));
+    RIDC_HIP_TRY(launch_1d_solo(h->solo, h->solo_blocks, h->threads, h->P, h->lds, s,
+                                h->stream));
   return RIDC_OK;
 }
 
@@ -538,6 +547,94 @@ int time_tile_1d(ridc_handle* h, const Tile1D& t, int reps, float* ms) {
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   return rc;
+}
+
+// Tiling of a grouped 1D launch: every system of the batch shares the thread count; a system
+// whose stored cycle has more than `rows` rows (rows > 0) is cut into chunks of at most `rows`
+// LDS rows including halos.  Tilings do not change results.
+Tile1D batch_tile_for(const ridc_handle* h, const BatchTile& bt, int threads) {
+  const ridc_problem& p = h->p;
+  const int64_t ms = p.bc == RIDC_BC_PERIODIC ? p.n : p.n + 2;
+  const Tile1D wrap{1, 0, threads};
+  const bool wrap_ok = tile_fits(&p, h->pcr, wrap);
+  if (wrap_ok && (bt.rows <= 0 || ms <= bt.rows)) return wrap;
+  const int64_t H = halo_rows(h->pcr);
+  if (bt.rows > 0 && bt.rows > 2 * H) {
+    const int64_t B = (bt.rows - 2 * H) / 64 * 64;
+    const Tile1D c{0, (int)std::min<int64_t>(B, 1 << 20), threads};
+    if (B >= 64 && tile_fits(&p, h->pcr, c)) return c;
+  }
+  if (wrap_ok) return wrap;
+  for (int B : {4096, 2048, 1024, 512, 256, kMinChunk}) {
+    const Tile1D c{0, B, threads};
+    if (tile_fits(&p, h->pcr, c)) return c;
+  }
+  return Tile1D{-1, 0, threads};
+}
+
+struct BatchStage {
+  int nblocks = 0, threads = 256, maxP = 1;
+  size_t lds = 0;
+};
+
+// Fill and upload the item and block tables of one grouped launch over the 1D handles hs.
+// Normal use: each handle's own step = launch step + its current sigma.  timing: every level
+// active from its start-up step on and never finishing (the rings are scratch).
+int stage_batch_1d(const std::vector<ridc_handle*>& hs, const BatchTile& bt, bool timing,
+                   hipStream_t stream, BatchStage* out) {
+  BatchStage st;
+  for (auto* h : hs) st.maxP = std::max(st.maxP, h->P);
+  st.threads = bt.threads;
+  if (st.threads == 1024 && st.maxP > kMaxJ1024 + 1) st.threads = 512;
+  std::vector<Tile1D> tiles(hs.size());
+  size_t nitems = 0, nblocks = 0;
+  for (size_t i = 0; i < hs.size(); ++i) {
+    tiles[i] = batch_tile_for(hs[i], bt, st.threads);
+    if (tiles[i].wrap < 0) return fail(RIDC_E_UNSUPPORTED, "no batch tiling fits a system");
+    const int64_t nch = tiles[i].wrap ? 1 : (hs[i]->p.n + tiles[i].B - 1) / tiles[i].B;
+    nitems += hs[i]->P;
+    nblocks += (size_t)(nch * hs[i]->P);
+  }
+  int rc = arena_reserve(nitems, nblocks);
+  if (rc != RIDC_OK) return rc;
+  std::vector<std::pair<int64_t, Blk1D>> order;
+  order.reserve(nblocks);
+  size_t ii = 0;
+  for (size_t i = 0; i < hs.size(); ++i) {
+    ridc_handle* h = hs[i];
+    const Tile1D& t = tiles[i];
+    const int64_t H = t.wrap ? 0 : halo_rows(h->pcr);
+    const int nch = t.wrap ? 1 : (int)((h->p.n + t.B - 1) / t.B);
+    const int64_t ms = h->p.bc == RIDC_BC_PERIODIC ? h->p.n : h->p.n + 2;
+    const int64_t rows = t.wrap ? ms : t.B + 2 * H;
+    for (int j = 0; j < h->P; ++j) {
+      Lvl1D it = h->proto[j];
+      it.nt = timing ? ((int64_t)1 << 40) : h->nt;
+      it.sigma0 = timing ? 0 : -h->sigma;
+      it.wrap = t.wrap;
+      it.B = t.wrap ? 0 : t.B;
+      it.H = (int32_t)H;
+      it.nchunks = nch;
+      g_arena.h_items[ii + j] = it;
+      st.lds = std::max(st.lds, lds_bytes_1d(it));
+      for (int c = 0; c < nch; ++c) order.push_back({rows, Blk1D{(int32_t)(ii + j), c}});
+    }
+    ii += h->P;
+  }
+  // the longest workgroups first
+  std::stable_sort(order.begin(), order.end(),
+                   [](const auto& a, const auto& b) { return a.first > b.first; });
+  for (size_t b = 0; b < order.size(); ++b) g_arena.h_blocks[b] = order[b].second;
+  st.nblocks = (int)order.size();
+  RIDC_HIP_TRY(prepare_1d_step(st.threads, st.maxP, st.lds));
+  RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_items, g_arena.h_items, sizeof(Lvl1D) * nitems,
+                              hipMemcpyHostToDevice, stream));
+  RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_blocks, g_arena.h_blocks, sizeof(Blk1D) * order.size(),
+                              hipMemcpyHostToDevice, stream));
+  RIDC_HIP_TRY(hipEventRecord(g_arena.done, stream));
+  g_arena.pending = true;
+  *out = st;
+  return RIDC_OK;
 }
 
 }  // namespace
@@ -791,57 +888,19 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
     }
   }
   if (!h1.empty()) {
-    size_t nitems = 0, nblocks = 0;
-    for (auto* h : h1) {
-      nitems += h->proto.size();
-      nblocks += std::max(h->blocks.size(), h->proto.size());
+    BatchTile bt;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      bt = g_batch_tile;
     }
-    rc = arena_reserve(nitems, nblocks);
+    BatchStage st;
+    rc = stage_batch_1d(h1, bt, false, stream, &st);
     if (rc != RIDC_OK) return rc;
-    // A batch keeps the GPU busy by itself, so every system uses its throughput tiling (the
-    // whole cycle in one workgroup when it fits: no halo recomputation), 256 threads, and the
-    // largest systems are dispatched first.  Tilings do not change results.
-    size_t ii = 0, bi = 0, lds = 0;
-    const int threads = 256;
-    std::vector<std::pair<int64_t, Blk1D>> order;
-    for (auto* h : h1) {
-      Tile1D wrap{1, 0, threads};
-      const bool use_wrap = tile_fits(&h->p, h->pcr, wrap);
-      for (size_t j = 0; j < h->proto.size(); ++j) {
-        Lvl1D it = h->proto[j];
-        it.nt = h->nt;
-        it.sigma0 = -h->sigma;  // the handle's own step = launch step + sigma
-        if (use_wrap) {
-          it.wrap = 1;
-          it.B = 0;
-          it.H = 0;
-          it.nchunks = 1;
-        }
-        g_arena.h_items[ii + j] = it;
-        lds = std::max(lds, lds_bytes_1d(it));
-        const int nch = use_wrap ? 1 : it.nchunks;
-        for (int c = 0; c < nch; ++c)
-          order.push_back({(int64_t)h->p.n * (use_wrap ? 1 : 0) + (use_wrap ? 0 : it.B + 2 * it.H),
-                           Blk1D{(int32_t)(ii + j), c}});
-      }
-      ii += h->proto.size();
-    }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const auto& a, const auto& b) { return a.first > b.first; });
-    nblocks = order.size();
-    for (auto& o : order) g_arena.h_blocks[bi++] = o.second;
-    RIDC_HIP_TRY(prepare_1d_step(threads, lds));
-    RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_items, g_arena.h_items, sizeof(Lvl1D) * nitems,
-                                hipMemcpyHostToDevice, stream));
-    RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_blocks, g_arena.h_blocks, sizeof(Blk1D) * nblocks,
-                                hipMemcpyHostToDevice, stream));
-    RIDC_HIP_TRY(hipEventRecord(g_arena.done, stream));
-    g_arena.pending = true;
     int64_t steps1 = 0;
     for (auto* h : h1) steps1 = std::max(steps1, std::min(max_steps, h->total - h->sigma));
     for (int64_t s = 1; s <= steps1; ++s)
-      RIDC_HIP_TRY(launch_1d_step(g_arena.d_items, g_arena.d_blocks, (int)nblocks, threads, lds,
-                                  s, stream));
+      RIDC_HIP_TRY(launch_1d_step(g_arena.d_items, g_arena.d_blocks, st.nblocks, st.threads,
+                                  st.maxP, st.lds, s, stream));
     for (auto* h : h1) h->sigma += std::min(max_steps, h->total - h->sigma);
   }
   // ---- 2D handles: grouped per step by the 2D planner -----------------------------------------
@@ -1028,6 +1087,85 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32
   if (threads_out) *threads_out = best.fused ? best.fused : best.threads;
   if (rows_out) *rows_out = best.wrap ? 0 : best.B;
   if (flags_out) *flags_out = best.nt_store | (best.fused ? 2 : 0);
+  return RIDC_OK;
+}
+
+int ridc_set_batch_tile(int32_t threads, int32_t rows) {
+  if (threads != 256 && threads != 512 && threads != 1024)
+    return fail(RIDC_E_INVAL, "batch threads must be 256, 512 or 1024");
+  if (rows < 0 || (rows > 0 && rows < 256)) return fail(RIDC_E_INVAL, "batch rows: 0 or >= 256");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_batch_tile = BatchTile{threads, rows};
+  return RIDC_OK;
+}
+
+int ridc_autotune_batch(ridc_handle* const* hs, int32_t count, int32_t* threads_out,
+                        int32_t* rows_out) {
+  int rc = check_handles(hs, count);
+  if (rc != RIDC_OK) return rc;
+  std::vector<ridc_handle*> h1;
+  for (int32_t i = 0; i < count; ++i)
+    if (hs[i]->p.dim == 1) h1.push_back(hs[i]);
+  BatchTile best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    best = g_batch_tile;
+  }
+  if (!h1.empty()) {
+    hipStream_t stream = h1[0]->stream;
+    // the timed steps overwrite the rings: start from zeros, leave the handles unarmed
+    for (auto* h : h1) {
+      int64_t slots = 0;
+      for (int j = 0; j < h->P; ++j) slots += h->R[j];
+      RIDC_HIP_TRY(hipMemsetAsync(h->ring[0], 0, sizeof(double) * (size_t)(slots * h->npts),
+                                  stream));
+      h->nt = -1;
+      h->sigma = h->total = 0;
+    }
+    int maxP = 1;
+    for (auto* h : h1) maxP = std::max(maxP, h->P);
+    const int64_t first = (int64_t)maxP * (maxP - 1) / 2 + 1;   // every level active
+    hipEvent_t a, b;
+    RIDC_HIP_TRY(hipEventCreate(&a));
+    RIDC_HIP_TRY(hipEventCreate(&b));
+    float best_ms = 1e30f;
+    constexpr int kReps = 20;
+    for (int T : {256, 512, 1024})
+      for (int rows : {0, 512, 768, 1024, 1536, 2048, 4096}) {
+        const BatchTile bt{T, rows};
+        BatchStage st;
+        rc = stage_batch_1d(h1, bt, true, stream, &st);
+        if (rc != RIDC_OK) break;
+        for (int64_t s = first; s < first + 3 && rc == RIDC_OK; ++s)   // warm-up
+          if (launch_1d_step(g_arena.d_items, g_arena.d_blocks, st.nblocks, st.threads, st.maxP,
+                             st.lds, s, stream) != hipSuccess)
+            rc = fail(RIDC_E_HIP, "batch tuning launch failed");
+        if (rc != RIDC_OK) break;
+        (void)hipEventRecord(a, stream);
+        for (int64_t s = first + 3; s < first + 3 + kReps && rc == RIDC_OK; ++s)
+          if (launch_1d_step(g_arena.d_items, g_arena.d_blocks, st.nblocks, st.threads, st.maxP,
+                             st.lds, s, stream) != hipSuccess)
+            rc = fail(RIDC_E_HIP, "batch tuning launch failed");
+        (void)hipEventRecord(b, stream);
+        if (rc != RIDC_OK) break;
+        float ms = 0;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+          rc = fail(RIDC_E_HIP, "batch tuning timing failed");
+          break;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = BatchTile{st.threads, rows};
+        }
+      }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != RIDC_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_batch_tile = best;
+  }
+  if (threads_out) *threads_out = best.threads;
+  if (rows_out) *rows_out = best.rows;
   return RIDC_OK;
 }
 

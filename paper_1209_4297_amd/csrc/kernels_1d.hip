@@ -259,34 +259,31 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
   }
 }
 
-// Levels above kMaxJ1024 are not instantiated in 1024-thread kernels (128 registers per
-// thread): the host never sends orders above kMaxJ1024 + 1 to them.
-template <int T>
+// Level j of a work item runs level_step<j>.  A kernel instantiates the levels up to MJ only
+// (the host picks MJ from the highest order in the launch), so that the register budget of an
+// order-4 launch is that of the level-3 body and not of the largest level; 1024-thread kernels
+// stop at kMaxJ1024 (128 registers per thread).
+template <int T, int MJ>
 __device__ __forceinline__ void dispatch_level(int j, const View& v, int chunk, int64_t m,
                                                double* lds, bool nt) {
   switch (j) {
     case 0: level_step<0, T>(v, chunk, m, lds, nt); break;
-    case 1: level_step<1, T>(v, chunk, m, lds, nt); break;
-    case 2: level_step<2, T>(v, chunk, m, lds, nt); break;
-    case 3: level_step<3, T>(v, chunk, m, lds, nt); break;
-    case 4: level_step<4, T>(v, chunk, m, lds, nt); break;
-    case 5: level_step<5, T>(v, chunk, m, lds, nt); break;
-    default:
-      if constexpr (T < 1024) {
-        switch (j) {
-          case 6: level_step<6, T>(v, chunk, m, lds, nt); break;
-          case 7: level_step<7, T>(v, chunk, m, lds, nt); break;
-          case 8: level_step<8, T>(v, chunk, m, lds, nt); break;
-          case 9: level_step<9, T>(v, chunk, m, lds, nt); break;
-          case 10: level_step<10, T>(v, chunk, m, lds, nt); break;
-          default: level_step<11, T>(v, chunk, m, lds, nt); break;
-        }
-      }
-      break;
+    case 1: if constexpr (MJ >= 1) level_step<1, T>(v, chunk, m, lds, nt); break;
+    case 2: if constexpr (MJ >= 2) level_step<2, T>(v, chunk, m, lds, nt); break;
+    case 3: if constexpr (MJ >= 3) level_step<3, T>(v, chunk, m, lds, nt); break;
+    case 4: if constexpr (MJ >= 4) level_step<4, T>(v, chunk, m, lds, nt); break;
+    case 5: if constexpr (MJ >= 5) level_step<5, T>(v, chunk, m, lds, nt); break;
+    case 6: if constexpr (MJ >= 6) level_step<6, T>(v, chunk, m, lds, nt); break;
+    case 7: if constexpr (MJ >= 7) level_step<7, T>(v, chunk, m, lds, nt); break;
+    case 8: if constexpr (MJ >= 8) level_step<8, T>(v, chunk, m, lds, nt); break;
+    case 9: if constexpr (MJ >= 9) level_step<9, T>(v, chunk, m, lds, nt); break;
+    case 10: if constexpr (MJ >= 10) level_step<10, T>(v, chunk, m, lds, nt); break;
+    case 11: if constexpr (MJ >= 11) level_step<11, T>(v, chunk, m, lds, nt); break;
+    default: break;
   }
 }
 
-template <int T>
+template <int T, int MJ>
 __global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
                                               const Blk1D* __restrict__ blocks, int64_t sigma) {
   extern __shared__ double lds[];
@@ -297,12 +294,12 @@ __global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
   if (m < 1 || m > L->nt) return;                                   // level idle this step
   View v{L->own, L->prev, L->W, L->gamma, L->shift, L->R_own, L->R_prev, L->n, L->M, L->bc,
          L->fe, L->stages, L->wrap, L->B, L->H, L->dt, L->ce, L->nu_h2, L->divisor};
-  dispatch_level<T>(j, v, bk.chunk, m, lds, false);
+  dispatch_level<T, MJ>(j, v, bk.chunk, m, lds, false);
 }
 
 // A single instance's step with every descriptor in the kernel arguments: block b handles level
 // b / nchunks, chunk b % nchunks, so the first memory access of a block is its data.
-template <int T>
+template <int T, int MJ>
 __global__ __launch_bounds__(T) void k_step1d_solo(const Solo1D a, int64_t sigma) {
   extern __shared__ double lds[];
   const int j = blockIdx.x / a.nchunks;
@@ -312,7 +309,7 @@ __global__ __launch_bounds__(T) void k_step1d_solo(const Solo1D a, int64_t sigma
   View v{a.ring[j], j > 0 ? a.ring[j - 1] : nullptr, a.W[j], a.gamma, a.shift, a.R[j],
          j > 0 ? a.R[j - 1] : 1, a.n, a.M, a.bc, a.fe, a.stages, a.wrap, a.B, a.H, a.dt,
          a.ce, a.nu_h2, a.divisor};
-  dispatch_level<T>(j, v, chunk, m, lds, a.nt_store != 0);
+  dispatch_level<T, MJ>(j, v, chunk, m, lds, a.nt_store != 0);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -476,14 +473,26 @@ size_t lds_bytes_1d(const Lvl1D& it) {
   return 2 * sizeof(double) * (size_t)(it.B + 2 * it.H);
 }
 
-template <int T>
-hipError_t allow_lds(size_t lds_bytes) {
+namespace {
+
+// Highest level index instantiated for a launch whose highest order is max_order: 3 (orders up
+// to 4), kMaxJ1024 (orders up to kMaxJ1024 + 1) or kMaxOrder - 1; -1 if no kernel of `threads`
+// threads covers it.
+int level_bound(int max_order, int threads) {
+  if (max_order <= 4) return 3;
+  if (max_order <= kMaxJ1024 + 1) return kMaxJ1024;
+  if (threads < 1024 && max_order <= kMaxOrder) return kMaxOrder - 1;
+  return -1;
+}
+
+template <int T, int MJ>
+hipError_t allow_lds_t(size_t lds_bytes) {
   static size_t allowed = 65536;
   if (lds_bytes > allowed) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step1d<T>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step1d<T, MJ>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step1d_solo<T>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step1d_solo<T, MJ>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
     allowed = lds_bytes;
@@ -491,71 +500,83 @@ hipError_t allow_lds(size_t lds_bytes) {
   return hipSuccess;
 }
 
-hipError_t prepare_1d_step(int threads, size_t lds_bytes) {
-  switch (threads) {
-    case 64: return allow_lds<64>(lds_bytes);
-    case 128: return allow_lds<128>(lds_bytes);
-    case 256: return allow_lds<256>(lds_bytes);
-    case 512: return allow_lds<512>(lds_bytes);
-    case 1024: return allow_lds<1024>(lds_bytes);
-    default: return hipErrorInvalidValue;
+template <int T, int MJ>
+hipError_t step_t(const Lvl1D* d_items, const Blk1D* d_blocks, const Solo1D* solo, int nblocks,
+                  size_t lds_bytes, int64_t sigma, hipStream_t stream) {
+  if (solo)
+    hipLaunchKernelGGL((k_step1d_solo<T, MJ>), dim3(nblocks), dim3(T), lds_bytes, stream, *solo,
+                       sigma);
+  else
+    hipLaunchKernelGGL((k_step1d<T, MJ>), dim3(nblocks), dim3(T), lds_bytes, stream, d_items,
+                       d_blocks, sigma);
+  return hipGetLastError();
+}
+
+// prepare (launch == false) or launch one step with T threads and the level bound of max_order
+template <int T>
+hipError_t step_threads(bool launch, int max_order, const Lvl1D* d_items, const Blk1D* d_blocks,
+                        const Solo1D* solo, int nblocks, size_t lds, int64_t sigma,
+                        hipStream_t stream) {
+  switch (level_bound(max_order, T)) {
+    case 3:
+      return launch ? step_t<T, 3>(d_items, d_blocks, solo, nblocks, lds, sigma, stream)
+                    : allow_lds_t<T, 3>(lds);
+    case kMaxJ1024:
+      return launch ? step_t<T, kMaxJ1024>(d_items, d_blocks, solo, nblocks, lds, sigma, stream)
+                    : allow_lds_t<T, kMaxJ1024>(lds);
+    case kMaxOrder - 1:
+      if constexpr (T < 1024)
+        return launch ? step_t<T, kMaxOrder - 1>(d_items, d_blocks, solo, nblocks, lds, sigma,
+                                                 stream)
+                      : allow_lds_t<T, kMaxOrder - 1>(lds);
+      return hipErrorInvalidValue;
+    default:
+      return hipErrorInvalidValue;
   }
+}
+
+hipError_t step_any(bool launch, int threads, int max_order, const Lvl1D* d_items,
+                    const Blk1D* d_blocks, const Solo1D* solo, int nblocks, size_t lds,
+                    int64_t sigma, hipStream_t stream) {
+  switch (threads) {
+    case 64:
+      return step_threads<64>(launch, max_order, d_items, d_blocks, solo, nblocks, lds, sigma,
+                              stream);
+    case 128:
+      return step_threads<128>(launch, max_order, d_items, d_blocks, solo, nblocks, lds, sigma,
+                               stream);
+    case 256:
+      return step_threads<256>(launch, max_order, d_items, d_blocks, solo, nblocks, lds, sigma,
+                               stream);
+    case 512:
+      return step_threads<512>(launch, max_order, d_items, d_blocks, solo, nblocks, lds, sigma,
+                               stream);
+    case 1024:
+      return step_threads<1024>(launch, max_order, d_items, d_blocks, solo, nblocks, lds, sigma,
+                                stream);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t prepare_1d_step(int threads, int max_order, size_t lds_bytes) {
+  return step_any(false, threads, max_order, nullptr, nullptr, nullptr, 0, lds_bytes, 0, nullptr);
 }
 
 hipError_t launch_1d_step(const Lvl1D* d_items, const Blk1D* d_blocks, int nblocks, int threads,
-                          size_t lds_bytes, int64_t sigma, hipStream_t stream) {
+                          int max_order, size_t lds_bytes, int64_t sigma, hipStream_t stream) {
   if (nblocks <= 0) return hipSuccess;
-  switch (threads) {
-    case 64:
-      hipLaunchKernelGGL(k_step1d<64>, dim3(nblocks), dim3(64), lds_bytes, stream, d_items,
-                         d_blocks, sigma);
-      break;
-    case 128:
-      hipLaunchKernelGGL(k_step1d<128>, dim3(nblocks), dim3(128), lds_bytes, stream, d_items,
-                         d_blocks, sigma);
-      break;
-    case 256:
-      hipLaunchKernelGGL(k_step1d<256>, dim3(nblocks), dim3(256), lds_bytes, stream, d_items,
-                         d_blocks, sigma);
-      break;
-    case 512:
-      hipLaunchKernelGGL(k_step1d<512>, dim3(nblocks), dim3(512), lds_bytes, stream, d_items,
-                         d_blocks, sigma);
-      break;
-    case 1024:
-      hipLaunchKernelGGL(k_step1d<1024>, dim3(nblocks), dim3(1024), lds_bytes, stream, d_items,
-                         d_blocks, sigma);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return step_any(true, threads, max_order, d_items, d_blocks, nullptr, nblocks, lds_bytes, sigma,
+                  stream);
 }
 
-hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, size_t lds_bytes,
-                          int64_t sigma, hipStream_t stream) {
+hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, int max_order,
+                          size_t lds_bytes, int64_t sigma, hipStream_t stream) {
   if (nblocks <= 0) return hipSuccess;
-  switch (threads) {
-    case 64:
-      hipLaunchKernelGGL(k_step1d_solo<64>, dim3(nblocks), dim3(64), lds_bytes, stream, a, sigma);
-      break;
-    case 128:
-      hipLaunchKernelGGL(k_step1d_solo<128>, dim3(nblocks), dim3(128), lds_bytes, stream, a, sigma);
-      break;
-    case 256:
-      hipLaunchKernelGGL(k_step1d_solo<256>, dim3(nblocks), dim3(256), lds_bytes, stream, a, sigma);
-      break;
-    case 512:
-      hipLaunchKernelGGL(k_step1d_solo<512>, dim3(nblocks), dim3(512), lds_bytes, stream, a, sigma);
-      break;
-    case 1024:
-      hipLaunchKernelGGL(k_step1d_solo<1024>, dim3(nblocks), dim3(1024), lds_bytes, stream, a,
-                         sigma);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return step_any(true, threads, max_order, nullptr, nullptr, &a, nblocks, lds_bytes, sigma,
+                  stream);
 }
 
 namespace {

@@ -116,18 +116,18 @@ struct Blk1D {
   int32_t chunk;
 };
 
-// Allow `lds_bytes` of dynamic LDS for the level-step kernel with `threads` threads (host call,
-// made when a tiling is chosen, never inside graph capture).
-hipError_t prepare_1d_step(int threads, size_t lds_bytes);
+// Allow `lds_bytes` of dynamic LDS for the level-step kernels with `threads` threads that cover
+// orders up to max_order (host call, made when a tiling is chosen, never inside graph capture).
+hipError_t prepare_1d_step(int threads, int max_order, size_t lds_bytes);
 
-// Launch one pipeline step of a grouped 1D batch.
+// Launch one pipeline step of a grouped 1D batch whose highest order is max_order.
 hipError_t launch_1d_step(const Lvl1D* d_items, const Blk1D* d_blocks, int nblocks, int threads,
-                          size_t lds_bytes, int64_t sigma, hipStream_t stream);
+                          int max_order, size_t lds_bytes, int64_t sigma, hipStream_t stream);
 
-// Launch one pipeline step of a single instance (descriptor in the kernel arguments); block b
-// covers level b / nchunks, chunk b % nchunks.
-hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, size_t lds_bytes,
-                          int64_t sigma, hipStream_t stream);
+// Launch one pipeline step of a single instance of order max_order (descriptor in the kernel
+// arguments); block b covers level b / nchunks, chunk b % nchunks.
+hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, int max_order,
+                          size_t lds_bytes, int64_t sigma, hipStream_t stream);
 
 // Launch the fused integration of `count` instances (one workgroup of `threads` = 512 or 1024
 // each, two LDS buffers of n (periodic) or n+2 (Dirichlet) doubles per level, level groups of

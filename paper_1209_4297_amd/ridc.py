@@ -75,6 +75,9 @@ def _load():
         "ridc_kernel_time": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_double)]),
         "ridc_integrate_restarts": (ctypes.c_int, [vp, dp, i64, i32, dp]),
+        "ridc_set_batch_tile": (ctypes.c_int, [i32, i32]),
+        "ridc_autotune_batch": (ctypes.c_int, [ctypes.POINTER(vp), i32, ctypes.POINTER(i32),
+                                               ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -88,7 +91,8 @@ EXPORTED = ("ridc_create", "ridc_destroy", "ridc_footprint_bytes", "ridc_integra
             "ridc_integrate_batch", "ridc_begin", "ridc_advance", "ridc_remaining", "ridc_read",
             "ridc_sync", "ridc_last_error", "ridc_quadrature_weights", "ridc_pcr_plan",
             "ridc_step_cost", "ridc_version", "ridc_autotune", "ridc_set_tile",
-            "ridc_kernel_time", "ridc_integrate_restarts")
+            "ridc_kernel_time", "ridc_integrate_restarts", "ridc_set_batch_tile",
+            "ridc_autotune_batch")
 
 
 def lib():
@@ -256,6 +260,21 @@ def integrate_batch(solvers, u0s, nsteps, uTs):
     _check(_lib.ridc_integrate_batch(_handle_array(solvers), n, u0a, nsa, uTa))
 
 
+def set_batch_tile(threads: int, rows: int):
+    """Tiling of grouped 1D launches: threads per workgroup and the most LDS rows per workgroup
+    (0: whole cycles).  Process-wide; results do not depend on it."""
+    _check(_lib.ridc_set_batch_tile(int(threads), int(rows)))
+
+
+def autotune_batch(solvers):
+    """Measure the grouped-launch tilings on these instances and keep the fastest; returns
+    (threads, rows).  The instances are left unarmed."""
+    t, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.ridc_autotune_batch(_handle_array(solvers), len(solvers), ctypes.byref(t),
+                                    ctypes.byref(r)))
+    return t.value, r.value
+
+
 def pipeline_steps(nt: int, order: int) -> int:
     return nt + order * (order - 1) // 2 if nt > 0 else 0
 
@@ -265,6 +284,7 @@ def grid_h(prob: dict) -> float:
     return prob["length"] / n if prob["bc"] == "periodic" else prob["length"] / (n + 1)
 
 
-__all__ = ["Ridc", "RidcError", "advance", "integrate_batch", "make_problem", "footprint_bytes",
+__all__ = ["Ridc", "RidcError", "advance", "integrate_batch", "set_batch_tile", "autotune_batch",
+           "make_problem", "footprint_bytes",
            "quadrature_weights", "pcr_plan", "pipeline_steps", "library_path", "lib", "EXPORTED",
            "math"]

@@ -120,3 +120,12 @@ def test_null_safety(ridc):
     assert lib.ridc_sync(None) == ridc.RIDC_E_INVAL
     assert lib.ridc_read(None, None, None) == ridc.RIDC_E_INVAL
     assert lib.ridc_advance(None, 0, 5) == 0
+
+
+def test_batch_tile_validation(ridc):
+    lib = ridc.lib()
+    for threads, rows in [(128, 0), (300, 0), (256, -1), (256, 100)]:
+        assert lib.ridc_set_batch_tile(threads, rows) == ridc.RIDC_E_INVAL
+    for threads, rows in [(1024, 768), (512, 0), (256, 0)]:
+        assert lib.ridc_set_batch_tile(threads, rows) == 0
+    assert lib.ridc_autotune_batch(None, 1, None, None) == ridc.RIDC_E_INVAL

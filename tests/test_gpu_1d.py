@@ -161,6 +161,42 @@ def test_batch_bitwise_equals_solo(env):
         s.close()
 
 
+@pytest.mark.parametrize("policy", [(256, 0), (512, 512), (1024, 768), (256, 1024), (1024, 0),
+                                    "tuned"])
+def test_batch_tilings_are_bitwise_identical(env, policy):
+    """Grouped launches cut long cycles into chunks, change the thread count, and use the
+    kernels specialised for the batch's highest order; none of it may change a bit."""
+    torch, ridc = env
+    cases = workloads.config_batched_1d(count=10, nt=60, T=0.015)
+    prob2, u02 = workloads.config_reacdiff_1d(n=2500, nt=50, order=3, T=0.03)
+    prob3, _ = workloads.config_advdiff_1d(n=512, nt=40, order=7, T=0.05)   # levels up to 6
+    u03 = workloads.fourier_modes_1d(512, np.random.default_rng(7))
+    cases = cases + [(prob2, u02), (prob3, u03)]
+    solvers, u0s, uTs, solo = [], [], [], []
+    for prob, u0 in cases:
+        s = ridc.Ridc(prob)
+        x0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+        solo.append(s.integrate(x0, prob["nt"]).cpu().numpy())
+        solvers.append(s)
+        u0s.append(x0)
+        uTs.append(torch.empty_like(x0))
+    nts = [p["nt"] for p, _ in cases]
+    try:
+        if policy == "tuned":
+            t, r = ridc.autotune_batch(solvers)
+            _say(f"batch tiling chosen: threads {t}, rows {r}")
+        else:
+            ridc.set_batch_tile(*policy)
+        ridc.integrate_batch(solvers, u0s, nts, uTs)
+        torch.cuda.synchronize()
+        for i, uT in enumerate(uTs):
+            np.testing.assert_array_equal(uT.cpu().numpy(), solo[i])
+    finally:
+        ridc.set_batch_tile(256, 0)
+        for s in solvers:
+            s.close()
+
+
 def test_graph_and_direct_launch_agree(env, monkeypatch):
     prob, u0 = workloads.config_reacdiff_1d(n=2048, nt=300, T=0.15)
     a, _ = run_gpu(env, prob, u0, levels=False)
