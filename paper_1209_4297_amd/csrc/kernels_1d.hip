@@ -47,13 +47,6 @@ __device__ __forceinline__ bool fe_stencil(int fe) {
   return fe == RIDC_FE_ADVECT_C2 || fe == RIDC_FE_ADVECT_UPWIND || fe == RIDC_FE_BURGERS;
 }
 
-// v at physical row p (-1 <= p <= n) under the grid's boundary rule
-__device__ __forceinline__ double at(const double* __restrict__ v, int p, int n, bool periodic) {
-  if (p < 0) return periodic ? v[p + n] : 0.0;
-  if (p >= n) return periodic ? v[p - n] : 0.0;
-  return v[p];
-}
-
 // Per-workgroup view of one level step of level J: where the level's value and the previous
 // level's window live this step, and the coefficients that fold eq. (corr) into one sum over the
 // window:
@@ -74,37 +67,76 @@ struct Geo {        // scalar problem data of a work item, copied out of the des
   double dt, ce, nu_h2;
 };
 
-template <int J>
-__device__ __forceinline__ double rhs_row(const Geo& G, const Step<J>& S, int p) {
-  const int n = G.n;
-  const double u0 = S.u[p];
-  double um = 0.0, up = 0.0;
-  if (fe_stencil(G.fe)) {
-    um = at(S.u, p - 1, n, G.per);
-    up = at(S.u, p + 1, n, G.per);
-  }
-  double acc = u0 + G.dt * fe_eval(G.fe, G.ce, um, u0, up);
-  if constexpr (J > 0) {
-#pragma unroll
-    for (int i = 0; i <= J; ++i) {
-      const double* v = S.v[i];
-      const double vm = at(v, p - 1, n, G.per);
-      const double v0 = v[p];
-      const double vp = at(v, p + 1, n, G.per);
-      const double li = G.nu_h2 * ((vm + vp) - 2.0 * v0);
-      acc += S.cf[i] * fe_eval(G.fe, G.ce, vm, v0, vp) + S.cl[i] * li;
-    }
-  }
-  return acc;
+// The value v holds in lane - 1 (wave_shr:1) or lane + 1 (wave_shl:1) of the wavefront, moved
+// as two 32-bit halves; lanes without a source receive 0.  All 64 lanes must be active.
+__device__ __forceinline__ double from_lane_below(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_lane_above(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
 
-// Right-hand side of row g of the odd (Dirichlet) or periodic cycle, g in [0, M).
+// Right-hand sides of the cycle rows gbase + l, l in [0, count), written to d[l] by the waves of
+// one workgroup (or level group): wave w of nw takes 62 consecutive rows per pass, its lane lam
+// holding row base + lam - 1.  Each lane loads one value of each vector (coalesced, all loads in
+// flight together) and takes its stencil neighbours from lanes lam -+ 1; lanes 0 and 63 only
+// supply neighbours.  Cycle rows map to grid rows as: periodic g -> g; Dirichlet (the odd
+// extension on M = 2n+2 rows) g in 1..n -> g - 1, mirror rows g >= n+2 -> M - g - 1 (the result
+// negated, the neighbours' roles swapped), ghost rows 0 and n+1 hold zero -- which is also the
+// value the zero-ghost stencil needs beyond either end.  Every row computes
+//   u + dt f_E(u) + sum_i [cf_i f_E(v_i) + cl_i L v_i]
+// at its grid row with the same operations in every tiling.  The pass loop is uniform per wave.
 template <int J>
-__device__ __forceinline__ double rhs_ext(const Geo& G, const Step<J>& S, int g) {
-  if (G.per) return rhs_row<J>(G, S, g);
-  if (g == 0 || g == G.n + 1) return 0.0;
-  if (g <= G.n) return rhs_row<J>(G, S, g - 1);
-  return -rhs_row<J>(G, S, G.M - g - 1);
+__device__ __forceinline__ void rhs_rows(const Geo& G, const Step<J>& S, int gbase, int count,
+                                         double* __restrict__ d, int wave, int nw, int lane) {
+  const int n = G.n, M = G.M;
+  for (int base = wave * 62; base < count; base += nw * 62) {
+    const int l = base + lane - 1;
+    // lanes past `count` are unused except row `count` as a neighbour: clamp, so that every
+    // cycle row lies in [gbase - 1, gbase + count], within (-M, 2M) for every caller
+    int g = gbase + (l < count ? l : count);
+    if (g < 0) g += M;
+    else if (g >= M) g -= M;
+    bool ghost = false, mir = false;
+    int p = g;
+    if (!G.per) {
+      ghost = g == 0 || g == n + 1;
+      mir = g > n + 1;
+      p = ghost ? 0 : (mir ? M - g - 1 : g - 1);
+    }
+    double u0 = S.u[p];
+    double v0[J + 1];                       // the window of level J-1 (none for the predictor)
+    if constexpr (J > 0) {
+#pragma unroll
+      for (int i = 0; i <= J; ++i) v0[i] = S.v[i][p];
+#pragma unroll
+      for (int i = 0; i <= J; ++i) v0[i] = ghost ? 0.0 : v0[i];
+    }
+    u0 = ghost ? 0.0 : u0;
+    double um = from_lane_below(u0), up = from_lane_above(u0);
+    if (mir) {
+      const double t = um;
+      um = up;
+      up = t;
+    }
+    double acc = u0 + G.dt * fe_eval(G.fe, G.ce, um, u0, up);
+#pragma unroll
+    for (int i = 0; i < (J > 0 ? J + 1 : 0); ++i) {
+      double vm = from_lane_below(v0[i]), vp = from_lane_above(v0[i]);
+      if (mir) {
+        const double t = vm;
+        vm = vp;
+        vp = t;
+      }
+      const double li = G.nu_h2 * ((vm + vp) - 2.0 * v0[i]);
+      acc += S.cf[i] * fe_eval(G.fe, G.ce, vm, v0[i], vp) + S.cl[i] * li;
+    }
+    if (lane >= 1 && lane <= 62 && l < count) d[l] = ghost ? 0.0 : (mir ? -acc : acc);
+  }
 }
 
 // Everything one level step reads besides the rings: built from a descriptor table entry
@@ -174,10 +206,8 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
     const int* __restrict__ shift = L.shift;
     double* d0 = lds;
     double* d1 = lds + ms;
-    for (int l = threadIdx.x; l < ms; l += T) {
-      d0[l] = rhs_ext<J>(G, S, l);
-      d1[l] = 0.0;
-    }
+    rhs_rows<J>(G, S, 0, ms, d0, threadIdx.x >> 6, T / 64, threadIdx.x & 63);
+    for (int l = threadIdx.x; l < ms; l += T) d1[l] = 0.0;
     __syncthreads();
     const int l0 = per ? 0 : 1, l1 = per ? n : n + 1;  // Dirichlet ghosts stay zero
     for (int k = 0; k < stages; ++k) {
@@ -213,12 +243,8 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
   const int g0 = (per ? 0 : 1) + chunk * B;
   double* d0 = lds;
   double* d1 = lds + E;
-  for (int l = threadIdx.x; l < E; l += T) {
-    int g = g0 - H + l;                               // in (-M, 2M): H < M, B + H <= n
-    if (g < 0) g += M;
-    if (g >= M) g -= M;
-    d0[l] = rhs_ext<J>(G, S, g);
-  }
+  // cycle rows g0 - H - 1 .. g0 + B + H lie in (-M, 2M): H < M and B + H <= n
+  rhs_rows<J>(G, S, g0 - H, E, d0, threadIdx.x >> 6, T / 64, threadIdx.x & 63);
   __syncthreads();
   // stages in pairs: stage k+1 of row l needs stage k at l and l +- 2s, i.e. the inputs at
   // l + t s, |t| <= 3 -- one barrier per pair, the same operations as one stage at a time
@@ -330,21 +356,7 @@ __device__ __forceinline__ void fused_rhs(const View& L, int64_t m, double* d, i
   Step<J> S;
   make_step<J>(L, m, g, S);
   const int ms = g.per ? g.n : g.n + 2;
-  constexpr int RB = 1;                       // rows whose loads are in flight together
-#pragma unroll 1
-  for (int base = lt; base < ms; base += RB * G) {
-    double v[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int l = base + r * G;
-      v[r] = l < ms ? rhs_ext<J>(g, S, l) : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int l = base + r * G;
-      if (l < ms) d[l] = v[r];
-    }
-  }
+  rhs_rows<J>(g, S, 0, ms, d, lt >> 6, G / 64, lt & 63);
 }
 
 template <int MJ>
