@@ -245,7 +245,8 @@ def bench_2d(args, torch, ridc):
 
 def bench_batched(args, torch, ridc):
     import workloads
-    cases = workloads.config_batched_1d()
+    cases = workloads.config_batched_1d(**({"nt": args.nt, "T": 0.25 * args.nt / 1000}
+                                          if args.nt else {}))
     steps, warmup = args.steps or 3, args.warmup if args.warmup is not None else 1
     solvers, u0s, uTs = [], [], []
     for prob, u0 in cases:
@@ -264,21 +265,11 @@ def bench_batched(args, torch, ridc):
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / steps
     total = sum(p["n"] for p, _ in cases) * cases[0][0]["nt"]
-    # roofline: one grouped launch of a steady-state step, events around single launches
+    # roofline: back-to-back grouped launches of one steady-state step (HIP events, library)
     for s, x0, nt in zip(solvers, u0s, nts):
         s.begin(x0, nt)
     ridc.advance(solvers, 6)
-    k = 50                                              # one table upload, then k launches
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
-    a.record(st)
-    ridc.advance(solvers, k)
-    b.record(st)
-    torch.cuda.synchronize()
-    us = a.elapsed_time(b) * 1e3 / k
-    bytes_per = sum(s.step_cost()[0] for s in solvers)
+    us, bytes_per = ridc.batch_kernel_time(solvers, args.reps)
     ach = bytes_per / (us * 1e-6) / 1e9
     roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_step1d (grouped)",

@@ -211,6 +211,16 @@ int ridc_autotune_batch(ridc_handle* const* hs, int32_t count, int32_t* threads_
 int ridc_kernel_time(ridc_handle* h, int32_t reps, double* us_per_launch,
                      double* work_per_launch);
 
+/* Average duration of one grouped 1D launch (section III-E's pipeline step for every instance in
+ * hs[0..count), with the current batch tiling), from HIP events around `reps` back-to-back
+ * launches on the handles' stream.  Every handle must be armed, 1D, not set to the whole-range
+ * workgroup, and have every level active in its next step, which each launch recomputes (the
+ * handles do not advance).  *bytes_per_launch (nullable) receives the algorithmic HBM bytes of
+ * that step summed over the instances (as ridc_step_cost).  Errors: RIDC_E_STATE,
+ * RIDC_E_UNSUPPORTED, RIDC_E_INVAL, RIDC_E_HIP.                                              */
+int ridc_batch_kernel_time(ridc_handle* const* hs, int32_t count, int32_t reps,
+                           double* us_per_launch, double* bytes_per_launch);
+
 /* Library version string.                                                                     */
 const char* ridc_version(void);
 

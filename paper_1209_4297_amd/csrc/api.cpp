@@ -364,6 +364,9 @@ struct BatchArena {
   Fused1D* d_fused = nullptr;
   Fused1D* h_fused = nullptr;
   size_t cap_fused = 0;
+  CopyItem* d_copy = nullptr;
+  CopyItem* h_copy = nullptr;
+  size_t cap_copy = 0;
   hipEvent_t done = nullptr;
   bool pending = false;
 };
@@ -428,12 +431,11 @@ int arena_reserve(size_t nitems, size_t nblocks) {
 
 int64_t pipeline_steps(int64_t nt, int P) { return nt > 0 ? nt + (int64_t)P * (P - 1) / 2 : 0; }
 
-int upload_solo_items(ridc_handle* h) {
+// The step count travels in the kernel arguments (single instance) or in the batch tables, so
+// arming a 1D handle touches host state only; the device item copy holds the PCR coefficients.
+void arm_solo_items(ridc_handle* h) {
   h->solo.nt = h->nt;
   for (auto& it : h->proto) it.nt = h->nt;
-  RIDC_HIP_TRY(hipMemcpyAsync(h->d_items, h->proto.data(), sizeof(Lvl1D) * h->proto.size(),
-                              hipMemcpyHostToDevice, h->stream));
-  return RIDC_OK;
 }
 
 int launch_solo_steps_1d(ridc_handle* h, int64_t first, int64_t last) {
@@ -637,6 +639,55 @@ int stage_batch_1d(const std::vector<ridc_handle*>& hs, const BatchTile& bt, boo
   return RIDC_OK;
 }
 
+// Validate and arm a handle for nsteps time steps (host state and 2D plan; the rings are
+// filled by the caller).
+int arm_handle(ridc_handle* h, const double* u0_dev, int64_t nsteps) {
+  if (!h || !u0_dev) return fail(RIDC_E_INVAL, "NULL handle or u0");
+  if (nsteps < 0) return fail(RIDC_E_INVAL, "nsteps must be >= 0");
+  if (nsteps > 0 && nsteps < h->P - 1)
+    return fail(RIDC_E_INVAL, "nsteps must be 0 or >= order-1 (start-up quadrature)");
+  h->nt = nsteps;
+  h->sigma = 0;
+  h->total = pipeline_steps(nsteps, h->P);
+  if (h->p.dim == 1) {
+    arm_solo_items(h);
+    return RIDC_OK;
+  }
+  return plan2d_arm(h->p2, nsteps, h->stream);
+}
+
+// Run a list of vector copies (optionally checking the copied values) as one launch, the list
+// going through the batch arena's pinned staging.
+int stage_copies(const std::vector<CopyItem>& c, hipStream_t stream) {
+  if (c.empty()) return RIDC_OK;
+  if (c.size() > 65535) return fail(RIDC_E_INVAL, "too many instances in one batch");
+  int rc = arena_reserve(0, 0);
+  if (rc != RIDC_OK) return rc;
+  if (c.size() > g_arena.cap_copy) {
+    if (g_arena.d_copy) (void)hipFree(g_arena.d_copy);
+    if (g_arena.h_copy) (void)hipHostFree(g_arena.h_copy);
+    g_arena.d_copy = nullptr;
+    g_arena.h_copy = nullptr;
+    const size_t cap = std::max<size_t>(c.size(), 2 * g_arena.cap_copy);
+    if (hipMalloc(&g_arena.d_copy, cap * sizeof(CopyItem)) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "batch copy table");
+    if (hipHostMalloc(&g_arena.h_copy, cap * sizeof(CopyItem), hipHostMallocDefault) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "batch copy staging");
+    g_arena.cap_copy = cap;
+  }
+  int64_t most = 0;
+  for (size_t i = 0; i < c.size(); ++i) {
+    g_arena.h_copy[i] = c[i];
+    most = std::max(most, c[i].n);
+  }
+  RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_copy, g_arena.h_copy, sizeof(CopyItem) * c.size(),
+                              hipMemcpyHostToDevice, stream));
+  RIDC_HIP_TRY(hipEventRecord(g_arena.done, stream));
+  g_arena.pending = true;
+  RIDC_HIP_TRY(launch_copy_items(g_arena.d_copy, (int)c.size(), most, stream));
+  return RIDC_OK;
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -778,9 +829,11 @@ int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out) {
       F.divisor = h->pcr.divisor;
     }
     if (hipMemcpy(h->d_blocks, h->blocks.data(), sizeof(Blk1D) * h->blocks.size(),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_items, h->proto.data(), sizeof(Lvl1D) * h->proto.size(),
                   hipMemcpyHostToDevice) != hipSuccess) {
       ridc_destroy(h);
-      return fail(RIDC_E_HIP, "block table upload failed");
+      return fail(RIDC_E_HIP, "item table upload failed");
     }
   } else {
     rc = plan2d_create(p, h->h, h->ring.data(), h->R.data(), h->W, h->woff.data(), cur, L.ws2d,
@@ -805,19 +858,13 @@ int ridc_destroy(ridc_handle* h) {
 }
 
 int ridc_begin(ridc_handle* h, const double* u0_dev, int64_t nsteps) {
-  if (!h || !u0_dev) return fail(RIDC_E_INVAL, "NULL handle or u0");
-  if (nsteps < 0) return fail(RIDC_E_INVAL, "nsteps must be >= 0");
-  if (nsteps > 0 && nsteps < h->P - 1)
-    return fail(RIDC_E_INVAL, "nsteps must be 0 or >= order-1 (start-up quadrature)");
+  int rc = arm_handle(h, u0_dev, nsteps);
+  if (rc != RIDC_OK) return rc;
   // every level starts from the initial data (section III-E, Fig. 2): slot 0 of each ring
   for (int j = 0; j < h->P; ++j)
     RIDC_HIP_TRY(hipMemcpyAsync(h->ring[j], u0_dev, sizeof(double) * h->npts,
                                 hipMemcpyDeviceToDevice, h->stream));
-  h->nt = nsteps;
-  h->sigma = 0;
-  h->total = pipeline_steps(nsteps, h->P);
-  if (h->p.dim == 1) return upload_solo_items(h);
-  return plan2d_arm(h->p2, nsteps, h->stream);
+  return RIDC_OK;
 }
 
 int64_t ridc_remaining(const ridc_handle* h) {
@@ -1009,19 +1056,33 @@ int ridc_integrate_batch(ridc_handle* const* hs, int32_t count, const double* co
   int rc = check_handles(hs, count);
   if (rc != RIDC_OK) return rc;
   if (count > 0 && (!u0 || !nsteps || !uT)) return fail(RIDC_E_INVAL, "NULL array argument");
+  if (count == 0) return RIDC_OK;
+  // arm every handle, then fill slot 0 of every level ring of every instance in one launch
+  // (every level starts from the initial data, section III-E)
   int64_t most = 0;
+  std::vector<CopyItem> copies;
   for (int32_t i = 0; i < count; ++i) {
-    rc = ridc_begin(hs[i], u0[i], nsteps[i]);
+    if (!uT[i]) return fail(RIDC_E_INVAL, "NULL output");
+    rc = arm_handle(hs[i], u0[i], nsteps[i]);
     if (rc != RIDC_OK) return rc;
     most = std::max(most, hs[i]->total);
+    for (int j = 0; j < hs[i]->P; ++j)
+      copies.push_back(CopyItem{u0[i], hs[i]->ring[j], hs[i]->npts, nullptr});
   }
+  hipStream_t stream = hs[0]->stream;
+  rc = stage_copies(copies, stream);
+  if (rc != RIDC_OK) return rc;
   rc = ridc_advance(hs, count, most);
   if (rc != RIDC_OK) return rc;
+  // the top level of every instance to its output, checked for non-finite values, in one launch
+  copies.clear();
   for (int32_t i = 0; i < count; ++i) {
-    rc = ridc_read(hs[i], uT[i], nullptr);
-    if (rc != RIDC_OK) return rc;
+    ridc_handle* h = hs[i];
+    const int top = h->P - 1;
+    copies.push_back(CopyItem{h->ring[top] + (h->nt % h->R[top]) * h->npts, uT[i], h->npts,
+                              h->flag});
   }
-  return RIDC_OK;
+  return stage_copies(copies, stream);
 }
 
 int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags) {
@@ -1166,6 +1227,63 @@ int ridc_autotune_batch(ridc_handle* const* hs, int32_t count, int32_t* threads_
   }
   if (threads_out) *threads_out = best.threads;
   if (rows_out) *rows_out = best.rows;
+  return RIDC_OK;
+}
+
+int ridc_batch_kernel_time(ridc_handle* const* hs, int32_t count, int32_t reps,
+                           double* us_per_launch, double* bytes_per_launch) {
+  int rc = check_handles(hs, count);
+  if (rc != RIDC_OK) return rc;
+  if (reps < 1 || !us_per_launch) return fail(RIDC_E_INVAL, "bad arguments");
+  std::vector<ridc_handle*> h1;
+  double bytes = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    ridc_handle* h = hs[i];
+    if (h->p.dim != 1) return fail(RIDC_E_UNSUPPORTED, "grouped 1D launches only");
+    if (h->nt < 0) return fail(RIDC_E_STATE, "handle not armed");
+    if (h->fused) return fail(RIDC_E_UNSUPPORTED, "handle uses the whole-range workgroup");
+    const int64_t first_full = (int64_t)h->P * (h->P - 1) / 2 + 1;
+    if (h->sigma + 1 < first_full || h->sigma + 1 - first_full + 1 > h->nt)
+      return fail(RIDC_E_STATE, "the next pipeline step does not have every level active");
+    double b = 0, f = 0;
+    rc = ridc_step_cost(h, &b, &f);
+    if (rc != RIDC_OK) return rc;
+    bytes += b;
+    h1.push_back(h);
+  }
+  if (h1.empty()) return fail(RIDC_E_INVAL, "no handles");
+  BatchTile bt;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    bt = g_batch_tile;
+  }
+  hipStream_t stream = h1[0]->stream;
+  BatchStage st;
+  rc = stage_batch_1d(h1, bt, false, stream, &st);
+  if (rc != RIDC_OK) return rc;
+  // the handles' next step, launched repeatedly: it recomputes the same values (its inputs are
+  // other ring slots), so the handles do not advance
+  for (int w = 0; w < 3; ++w)
+    RIDC_HIP_TRY(launch_1d_step(g_arena.d_items, g_arena.d_blocks, st.nblocks, st.threads,
+                                st.maxP, st.lds, 1, stream));
+  hipEvent_t a, b;
+  RIDC_HIP_TRY(hipEventCreate(&a));
+  RIDC_HIP_TRY(hipEventCreate(&b));
+  (void)hipEventRecord(a, stream);
+  for (int32_t r = 0; r < reps && rc == RIDC_OK; ++r)
+    if (launch_1d_step(g_arena.d_items, g_arena.d_blocks, st.nblocks, st.threads, st.maxP,
+                       st.lds, 1, stream) != hipSuccess)
+      rc = fail(RIDC_E_HIP, "grouped launch failed");
+  (void)hipEventRecord(b, stream);
+  float ms = 0;
+  if (rc == RIDC_OK &&
+      (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
+    rc = fail(RIDC_E_HIP, "event timing failed");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc != RIDC_OK) return rc;
+  *us_per_launch = 1e3 * (double)ms / reps;
+  if (bytes_per_launch) *bytes_per_launch = bytes;
   return RIDC_OK;
 }
 

@@ -475,7 +475,32 @@ __global__ void k_nonfinite(const double* __restrict__ x, int64_t count, int* fl
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
+// Item blockIdx.y of a copy list, strided over blockIdx.x; flags non-finite values when asked.
+__global__ void k_copy_items(const CopyItem* __restrict__ items) {
+  const CopyItem it = items[blockIdx.y];
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < it.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = it.src[i];
+    it.dst[i] = v;
+    if (!(v - v == 0.0)) bad = 1;      // NaN or Inf
+  }
+  if (it.flag && __any(bad) && (threadIdx.x & 63) == 0) atomicOr(it.flag, 1);
+}
+
 }  // namespace
+
+hipError_t launch_copy_items(const CopyItem* d_items, int count, int64_t max_n,
+                             hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  int64_t bx = (max_n + 1023) / 1024;
+  if (bx < 1) bx = 1;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_copy_items, dim3((unsigned)bx, (unsigned)count), dim3(256), 0, stream,
+                     d_items);
+  return hipGetLastError();
+}
 
 size_t lds_bytes_1d(const Lvl1D& it) {
   if (it.wrap) {

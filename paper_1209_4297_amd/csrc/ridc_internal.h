@@ -137,6 +137,19 @@ hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, int max_ord
 hipError_t launch_fused_1d(const Fused1D* d_items, const Fused1D* one, int count, int max_order,
                            int threads, size_t lds_bytes, hipStream_t stream);
 
+// One vector copy of a batched copy launch: dst[0..n) = src[0..n); if flag is not null, *flag is
+// set to 1 when a copied value is not finite.
+struct CopyItem {
+  const double* src;
+  double* dst;
+  int64_t n;
+  int* flag;
+};
+
+// Copy every item of d_items[0..count) (count <= 65535; max_n: the longest item) in one launch.
+hipError_t launch_copy_items(const CopyItem* d_items, int count, int64_t max_n,
+                             hipStream_t stream);
+
 // Set *flag to 1 if any of x[0..count) is not finite.
 hipError_t launch_nonfinite_check(const double* x, int64_t count, int* flag, hipStream_t stream);
 

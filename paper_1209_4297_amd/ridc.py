@@ -76,6 +76,9 @@ def _load():
                                             ctypes.POINTER(ctypes.c_double)]),
         "ridc_integrate_restarts": (ctypes.c_int, [vp, dp, i64, i32, dp]),
         "ridc_set_batch_tile": (ctypes.c_int, [i32, i32]),
+        "ridc_batch_kernel_time": (ctypes.c_int, [ctypes.POINTER(vp), i32, i32,
+                                                  ctypes.POINTER(ctypes.c_double),
+                                                  ctypes.POINTER(ctypes.c_double)]),
         "ridc_autotune_batch": (ctypes.c_int, [ctypes.POINTER(vp), i32, ctypes.POINTER(i32),
                                                ctypes.POINTER(i32)]),
     }
@@ -92,7 +95,7 @@ EXPORTED = ("ridc_create", "ridc_destroy", "ridc_footprint_bytes", "ridc_integra
             "ridc_sync", "ridc_last_error", "ridc_quadrature_weights", "ridc_pcr_plan",
             "ridc_step_cost", "ridc_version", "ridc_autotune", "ridc_set_tile",
             "ridc_kernel_time", "ridc_integrate_restarts", "ridc_set_batch_tile",
-            "ridc_autotune_batch")
+            "ridc_autotune_batch", "ridc_batch_kernel_time")
 
 
 def lib():
@@ -275,6 +278,14 @@ def autotune_batch(solvers):
     return t.value, r.value
 
 
+def batch_kernel_time(solvers, reps: int):
+    """(us per grouped launch, algorithmic bytes per launch) of the armed instances' next step."""
+    us, b = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.ridc_batch_kernel_time(_handle_array(solvers), len(solvers), int(reps),
+                                       ctypes.byref(us), ctypes.byref(b)))
+    return us.value, b.value
+
+
 def pipeline_steps(nt: int, order: int) -> int:
     return nt + order * (order - 1) // 2 if nt > 0 else 0
 
@@ -285,6 +296,7 @@ def grid_h(prob: dict) -> float:
 
 
 __all__ = ["Ridc", "RidcError", "advance", "integrate_batch", "set_batch_tile", "autotune_batch",
+           "batch_kernel_time",
            "make_problem", "footprint_bytes",
            "quadrature_weights", "pcr_plan", "pipeline_steps", "library_path", "lib", "EXPORTED",
            "math"]

@@ -224,6 +224,27 @@ def test_nonfinite_is_reported(env):
     s.close()
 
 
+def test_batch_reports_nonfinite_per_instance(env):
+    """A batched integration flags the instance whose result is not finite, and only it."""
+    torch, ridc = env
+    cases = [workloads.config_advdiff_1d(n=n, nt=20) for n in (64, 256, 100)]
+    solvers = [ridc.Ridc(p) for p, _ in cases]
+    u0s = [torch.tensor(u, dtype=torch.float64, device="cuda") for _, u in cases]
+    u0s[1][17] = float("nan")
+    uTs = [torch.empty_like(x) for x in u0s]
+    ridc.integrate_batch(solvers, u0s, [20, 20, 20], uTs)
+    solvers[0].sync()
+    solvers[2].sync()
+    with pytest.raises(ridc.RidcError) as ei:
+        solvers[1].sync()
+    assert ei.value.code == ridc.RIDC_E_NONFINITE
+    for i in (0, 2):
+        alone = solvers[i].integrate(u0s[i], 20)
+        assert torch.equal(alone, uTs[i])
+    for s in solvers:
+        s.close()
+
+
 def test_state_errors(env):
     torch, ridc = env
     prob, u0 = workloads.config_advdiff_1d(n=64, nt=20)
