@@ -196,6 +196,15 @@ def bench_2d(args, torch, ridc):
     steps, warmup = args.steps or 3, args.warmup if args.warmup is not None else 1
     el, out, s, x0, _ = run_single(args, torch, ridc, prob, u0, args.prec, steps, warmup)
     roof = roofline_single(ridc, s, x0, nt, max(10, args.reps // 10), "mfma", args.prec)
+    # the stencil/quadrature kernel of the same step is HBM-bound: its own roofline
+    s.begin(x0, nt)
+    ridc.advance([s], P * (P - 1) // 2)
+    us_rhs, bytes_rhs = s.stencil_time(max(10, args.reps // 10))
+    s.sync()
+    ach_rhs = bytes_rhs / (us_rhs * 1e-6) / 1e9
+    roof_rhs = {"bound": "hbm", "achieved": round(ach_rhs, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach_rhs / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": "k_rhs2d", "launch_us": round(us_rhs, 3), "bytes_per_launch": bytes_rhs}
     s.close()
     check = {}
     golden = os.path.join(ROOT, "tests", "golden", "reacdiff2d_n1024_nt500.npz")
@@ -240,7 +249,7 @@ def bench_2d(args, torch, ridc):
                        "bf16x3": "bf16x3 transforms, f64 sums"}[args.prec],
                 config={"workload": desc, "n": n, "nt": nt, "order": P, "prec": args.prec,
                         "pipeline_steps": nt + P * (P - 1) // 2},
-                roofline=roof, cpu=cpu, check=check)
+                roofline=roof, roofline_stencil=roof_rhs, cpu=cpu, check=check)
 
 
 def bench_batched(args, torch, ridc):
@@ -400,6 +409,8 @@ def run_workload(args, torch, ridc):
         "roofline": r["roofline"],
         "cpu_baseline": r["cpu"],
     }
+    if r.get("roofline_stencil"):
+        line["roofline_stencil"] = r["roofline_stencil"]
     return line
 
 

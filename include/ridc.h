@@ -221,6 +221,16 @@ int ridc_kernel_time(ridc_handle* h, int32_t reps, double* us_per_launch,
 int ridc_batch_kernel_time(ridc_handle* const* hs, int32_t count, int32_t reps,
                            double* us_per_launch, double* bytes_per_launch);
 
+/* 2D: average duration of the right-hand-side kernel (the stencils and the quadrature of
+ * eq. (corr) over the window, section III-C, plus the explicit-term differences, for every
+ * level) at the handle's next pipeline step, which must have every level active, from HIP events
+ * around `reps` back-to-back launches on the handle's stream (each rewrites the same values; the
+ * handle does not advance).  *bytes_per_launch (nullable) receives its algorithmic HBM bytes.
+ * Errors: RIDC_E_UNSUPPORTED for 1D handles (their stencils are fused into the level step),
+ * RIDC_E_STATE, RIDC_E_INVAL.                                                                */
+int ridc_stencil_time(ridc_handle* h, int32_t reps, double* us_per_launch,
+                      double* bytes_per_launch);
+
 /* Library version string.                                                                     */
 const char* ridc_version(void);
 

@@ -1287,6 +1287,23 @@ int ridc_batch_kernel_time(ridc_handle* const* hs, int32_t count, int32_t reps,
   return RIDC_OK;
 }
 
+int ridc_stencil_time(ridc_handle* h, int32_t reps, double* us_per_launch,
+                      double* bytes_per_launch) {
+  if (!h || reps < 1 || !us_per_launch) return fail(RIDC_E_INVAL, "bad arguments");
+  if (h->p.dim != 2)
+    return fail(RIDC_E_UNSUPPORTED, "1D stencils are fused into the level-step kernel");
+  if (h->nt < 0) return fail(RIDC_E_STATE, "handle not armed");
+  const int64_t s = h->sigma + 1;
+  const int64_t first_full = (int64_t)h->P * (h->P - 1) / 2 + 1;
+  if (s < first_full || s - first_full + 1 > h->nt)
+    return fail(RIDC_E_STATE, "the next pipeline step does not have every level active");
+  double bytes = 0;
+  int rc = plan2d_time_rhs(h->p2, s, reps, h->stream, us_per_launch, &bytes);
+  if (rc != RIDC_OK) return rc;
+  if (bytes_per_launch) *bytes_per_launch = bytes;
+  return RIDC_OK;
+}
+
 int ridc_kernel_time(ridc_handle* h, int32_t reps, double* us_per_launch, double* work_per_launch) {
   if (!h || reps < 1 || !us_per_launch) return fail(RIDC_E_INVAL, "bad arguments");
   if (h->nt < 0) return fail(RIDC_E_STATE, "handle not armed");

@@ -793,6 +793,38 @@ int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, do
   return RIDC_OK;
 }
 
+int plan2d_time_rhs(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us,
+                    double* bytes) {
+  const int P = pl->P;
+  const int64_t n = pl->n;
+  const unsigned gx = (unsigned)((n + 63) / 64), gy = (unsigned)((n + 3) / 4);
+  // the right-hand side of this step, launched repeatedly (it rewrites the same values)
+  hipLaunchKernelGGL(k_rhs2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, sigma);
+  hipEvent_t a, b;
+  RIDC_HIP_TRY(hipEventCreate(&a));
+  RIDC_HIP_TRY(hipEventCreate(&b));
+  (void)hipEventRecord(a, stream);
+  for (int r = 0; r < reps; ++r)
+    hipLaunchKernelGGL(k_rhs2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, sigma);
+  (void)hipEventRecord(b, stream);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(RIDC_E_HIP, std::string("rhs timing: ") + hipGetErrorString(e));
+  *us = 1e3 * (double)ms / reps;
+  // algorithmic bytes per point: level 0 reads its value (a 5-point stencil of one vector),
+  // level j > 0 its value and j+1 window vectors; every level writes the FP64 right-hand side
+  // and, in the mixed paths, its 4-byte low-precision copy
+  const double lo = pl->prec == PREC_F64 ? 0.0 : 4.0;
+  double per = 0.0;
+  for (int j = 0; j < P; ++j) per += 8.0 * (j == 0 ? 1 : j + 2) + 8.0 + lo;
+  *bytes = per * (double)n * (double)n;
+  return RIDC_OK;
+}
+
 void plan2d_cost(const Plan2D* pl, double* bytes, double* flops) {
   const double n = (double)pl->n;
   const int passes = pl->prec == PREC_F64 ? 4 : 8;

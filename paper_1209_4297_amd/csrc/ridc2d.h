@@ -26,5 +26,9 @@ void plan2d_cost(const Plan2D* pl, double* bytes, double* flops);
 // Average duration (us) of `reps` back-to-back launches of the first transform pass of step
 // `sigma` (every level active), after computing that step's right-hand side once.
 int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us);
+// Average duration (us) of `reps` back-to-back launches of the right-hand-side kernel of step
+// `sigma` (every level active) and its algorithmic HBM bytes per launch.
+int plan2d_time_rhs(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us,
+                    double* bytes);
 
 }  // namespace ridc

@@ -76,6 +76,8 @@ def _load():
                                             ctypes.POINTER(ctypes.c_double)]),
         "ridc_integrate_restarts": (ctypes.c_int, [vp, dp, i64, i32, dp]),
         "ridc_set_batch_tile": (ctypes.c_int, [i32, i32]),
+        "ridc_stencil_time": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double)]),
         "ridc_batch_kernel_time": (ctypes.c_int, [ctypes.POINTER(vp), i32, i32,
                                                   ctypes.POINTER(ctypes.c_double),
                                                   ctypes.POINTER(ctypes.c_double)]),
@@ -95,7 +97,7 @@ EXPORTED = ("ridc_create", "ridc_destroy", "ridc_footprint_bytes", "ridc_integra
             "ridc_sync", "ridc_last_error", "ridc_quadrature_weights", "ridc_pcr_plan",
             "ridc_step_cost", "ridc_version", "ridc_autotune", "ridc_set_tile",
             "ridc_kernel_time", "ridc_integrate_restarts", "ridc_set_batch_tile",
-            "ridc_autotune_batch", "ridc_batch_kernel_time")
+            "ridc_autotune_batch", "ridc_batch_kernel_time", "ridc_stencil_time")
 
 
 def lib():
@@ -235,6 +237,14 @@ class Ridc:
         w = ctypes.c_double()
         _check(_lib.ridc_kernel_time(self._h, int(reps), ctypes.byref(us), ctypes.byref(w)))
         return us.value, w.value
+
+    def stencil_time(self, reps: int = 50):
+        """2D: (us per launch, algorithmic bytes per launch) of the right-hand-side kernel at
+        the next pipeline step."""
+        us = ctypes.c_double()
+        b = ctypes.c_double()
+        _check(_lib.ridc_stencil_time(self._h, int(reps), ctypes.byref(us), ctypes.byref(b)))
+        return us.value, b.value
 
     def step_cost(self):
         b = ctypes.c_double()
