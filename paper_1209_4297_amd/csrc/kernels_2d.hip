@@ -219,8 +219,54 @@ struct Tr<PREC_BF16> {
 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-template <int PREC, int OUT>
+// Folding by the reflection symmetry of the sine matrix, Q_{n-1-k, j} = (-1)^j Q_{k, j}:
+//   (A Q)_{ij} = sum_{k < n/2} (A_{ik} + (-1)^j A_{i, n-1-k}) Q_{kj},
+// so the even output columns take the sums and the odd ones the differences of mirrored columns
+// of A, against half of Q.  a holds columns k .. k+e-1 of a row, m the mirrored chunk
+// n-k-e .. n-k-1 (its elements in reverse order pair with a's).
+__device__ __forceinline__ void fold_f64(u32x4 a, u32x4 m, u32x4* sum, u32x4* dif) {
+  const dbl2 x = __builtin_bit_cast(dbl2, a), y = __builtin_bit_cast(dbl2, m);
+  *sum = __builtin_bit_cast(u32x4, dbl2{x[0] + y[1], x[1] + y[0]});
+  *dif = __builtin_bit_cast(u32x4, dbl2{x[0] - y[1], x[1] - y[0]});
+}
+__device__ __forceinline__ void fold_f32(u32x4 a, u32x4 m, u32x4* sum, u32x4* dif) {
+  const flt4 x = __builtin_bit_cast(flt4, a), y = __builtin_bit_cast(flt4, m);
+  *sum = __builtin_bit_cast(u32x4, flt4{x[0] + y[3], x[1] + y[2], x[2] + y[1], x[3] + y[0]});
+  *dif = __builtin_bit_cast(u32x4, flt4{x[0] - y[3], x[1] - y[2], x[2] - y[1], x[3] - y[0]});
+}
+__device__ __forceinline__ float bf_to_f(unsigned short b) {
+  return __builtin_bit_cast(float, (unsigned int)b << 16);
+}
+// split BF16 operands (hi, lo): the folded values are formed in FP32 and split again
+__device__ __forceinline__ void fold_bf16(u32x4 ah, u32x4 al, u32x4 mh, u32x4 ml, u32x4* sh,
+                                          u32x4* sl, u32x4* dh, u32x4* dl) {
+  const u16x8 xh = __builtin_bit_cast(u16x8, ah), xl = __builtin_bit_cast(u16x8, al);
+  const u16x8 yh = __builtin_bit_cast(u16x8, mh), yl = __builtin_bit_cast(u16x8, ml);
+  u16x8 osh, osl, odh, odl;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float x = bf_to_f(xh[e]) + bf_to_f(xl[e]);
+    const float y = bf_to_f(yh[7 - e]) + bf_to_f(yl[7 - e]);
+    const float su = x + y, di = x - y;
+    const __bf16 suh = (__bf16)su, dih = (__bf16)di;
+    osh[e] = __builtin_bit_cast(unsigned short, suh);
+    osl[e] = __builtin_bit_cast(unsigned short, (__bf16)(su - (float)suh));
+    odh[e] = __builtin_bit_cast(unsigned short, dih);
+    odl[e] = __builtin_bit_cast(unsigned short, (__bf16)(di - (float)dih));
+  }
+  *sh = __builtin_bit_cast(u32x4, osh);
+  *sl = __builtin_bit_cast(u32x4, osl);
+  *dh = __builtin_bit_cast(u32x4, odh);
+  *dl = __builtin_bit_cast(u32x4, odl);
+}
+
+// FOLD (n a multiple of 64): the contraction runs over k < n/2 with the folded A operands and
+// E.Q the folded transform: row j' (n rows) holds Q_{k, perm(j')} for k < n/2, perm(j') = 2j'
+// for j' < n/2 and 2(j' - n/2) + 1 above; output column j' of the block grid is column perm(j').
+template <int PREC, int OUT, int FOLD>
 __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ passes,
                                                  const Lvl2D* __restrict__ levels, int64_t sigma) {
   typedef Tr<PREC> TR;
@@ -232,7 +278,8 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   constexpr int CH = BK * (int)sizeof(T) / 16;        // 16-byte chunks per row
   constexpr int NSPLIT = PREC == PREC_BF16 ? 2 : 1;
   constexpr int CPT = BT * CH / NTHR;                 // chunks per thread per operand and split
-  __shared__ __attribute__((aligned(16))) T As[NSPLIT][BT * LDE];
+  constexpr int NA = FOLD ? 2 : 1;                    // A operands: (folded sums, differences)
+  __shared__ __attribute__((aligned(16))) T As[NA][NSPLIT][BT * LDE];
   __shared__ __attribute__((aligned(16))) T Bs[NSPLIT][BT * LDE];
 
   const Pass2D& E = passes[blockIdx.z];
@@ -246,6 +293,9 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   const int64_t nn = (int64_t)n * n;
   const T* A = (const T*)E.A;
   const T* Q = (const T*)E.Q;
+  const int K = FOLD ? n / 2 : n;                   // contraction length
+  const int64_t qsplit = (int64_t)n * K;            // BF16: lo part of the transform
+  constexpr int E16 = 16 / (int)sizeof(T);          // elements per 16-byte chunk
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -259,7 +309,7 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-  u32x4 ra[NSPLIT][CPT], rb[NSPLIT][CPT];
+  u32x4 ra[NSPLIT][CPT], rm[NSPLIT][CPT], rb[NSPLIT][CPT];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int s = 0; s < NSPLIT; ++s)
@@ -268,24 +318,51 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
         const int id = tid + c * NTHR;
         const int r = id / CH, q = id % CH;
         const int ga = row0 + r, gb = col0 + r;         // Q symmetric: row j of Q = column j
-        const int64_t ko = k0 + q * (16 / (int)sizeof(T));
-        ra[s][c] = ga < n ? *(const u32x4*)(A + s * nn + (int64_t)ga * n + ko) : u32x4{0, 0, 0, 0};
-        rb[s][c] = gb < n ? *(const u32x4*)(Q + s * nn + (int64_t)gb * n + ko) : u32x4{0, 0, 0, 0};
+        const int64_t ko = k0 + q * E16;
+        const T* arow = A + s * nn + (int64_t)ga * n;
+        ra[s][c] = ga < n ? *(const u32x4*)(arow + ko) : u32x4{0, 0, 0, 0};
+        if constexpr (FOLD)
+          rm[s][c] = ga < n ? *(const u32x4*)(arow + (n - ko - E16)) : u32x4{0, 0, 0, 0};
+        rb[s][c] = gb < n ? *(const u32x4*)(Q + s * qsplit + (int64_t)gb * K + ko)
+                          : u32x4{0, 0, 0, 0};
       }
   };
   auto sstore = [&]() {
 #pragma unroll
-    for (int s = 0; s < NSPLIT; ++s)
+    for (int c = 0; c < CPT; ++c) {
+      const int id = tid + c * NTHR;
+      const int r = id / CH, q = id % CH;
+      const int off = r * ROWB + q * 16;
+      if constexpr (!FOLD) {
 #pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        const int id = tid + c * NTHR;
-        const int r = id / CH, q = id % CH;
-        *(u32x4*)((char*)As[s] + r * ROWB + q * 16) = ra[s][c];
-        *(u32x4*)((char*)Bs[s] + r * ROWB + q * 16) = rb[s][c];
+        for (int s = 0; s < NSPLIT; ++s) *(u32x4*)((char*)As[0][s] + off) = ra[s][c];
+      } else if constexpr (PREC == PREC_BF16) {
+        u32x4 sh, sl, dh, dl;
+        fold_bf16(ra[0][c], ra[1][c], rm[0][c], rm[1][c], &sh, &sl, &dh, &dl);
+        *(u32x4*)((char*)As[0][0] + off) = sh;
+        *(u32x4*)((char*)As[0][1] + off) = sl;
+        *(u32x4*)((char*)As[1][0] + off) = dh;
+        *(u32x4*)((char*)As[1][1] + off) = dl;
+      } else {
+        u32x4 su, di;
+        if constexpr (PREC == PREC_F64)
+          fold_f64(ra[0][c], rm[0][c], &su, &di);
+        else
+          fold_f32(ra[0][c], rm[0][c], &su, &di);
+        *(u32x4*)((char*)As[0][0] + off) = su;
+        *(u32x4*)((char*)As[1][0] + off) = di;
       }
+#pragma unroll
+      for (int s = 0; s < NSPLIT; ++s) *(u32x4*)((char*)Bs[s] + off) = rb[s][c];
+    }
   };
 
-  const int KT = n / BK;
+  // the A operand of each 16-column group of this wave: sums (0) for even output columns,
+  // differences (1) for odd ones -- uniform per group since n/2 is a multiple of 32
+  const int half = n >> 1;
+  const int pa0 = FOLD && col0 + wn >= half ? 1 : 0;
+  const int pa1 = FOLD && col0 + wn + 16 >= half ? 1 : 0;
+  const int KT = K / BK;
   const int r16 = lane & 15;
   gload(0);
   for (int kt = 0; kt < KT; ++kt) {
@@ -296,12 +373,19 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
     if constexpr (PREC == PREC_BF16) {
       // lane holds 8 consecutive k of row (l % 16), k offset 8 (l / 16)
       const int kb = (lane >> 4) * 16;                 // byte offset of the 8 k values
-      bf16x8 ahi[4], alo[4], bhi[2], blo[2];
+      bf16x8 ahi[2][4], alo[2][4], bhi[2], blo[2];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int ro = (wm + t * 16 + r16) * ROWB + kb;
-        ahi[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[0] + ro));
-        alo[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[1] + ro));
+        ahi[0][t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa0][0] + ro));
+        alo[0][t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa0][1] + ro));
+        if (pa1 != pa0) {
+          ahi[1][t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa1][0] + ro));
+          alo[1][t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa1][1] + ro));
+        } else {
+          ahi[1][t] = ahi[0][t];
+          alo[1][t] = alo[0][t];
+        }
       }
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
@@ -313,18 +397,22 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[a], bhi[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], blo[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], bhi[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[b][a], bhi[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[b][a], blo[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[b][a], bhi[b], acc[a][b], 0, 0, 0);
         }
     } else {
       // k-steps of 4: lane holds element (row l % 16, k l / 16)
       const int k4 = lane >> 4;
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        T af[4], bf[2];
+        T af[2][4], bf[2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) af[t] = As[0][(wm + t * 16 + r16) * LDE + kk + k4];
+        for (int t = 0; t < 4; ++t) {
+          const int ai = (wm + t * 16 + r16) * LDE + kk + k4;
+          af[0][t] = As[pa0][0][ai];
+          af[1][t] = pa1 != pa0 ? As[pa1][0][ai] : af[0][t];
+        }
 #pragma unroll
         for (int t = 0; t < 2; ++t) bf[t] = Bs[0][(wn + t * 16 + r16) * LDE + kk + k4];
 #pragma unroll
@@ -332,9 +420,9 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
             if constexpr (PREC == PREC_F64)
-              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[b][a], bf[b], acc[a][b], 0, 0, 0);
             else
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[b][a], bf[b], acc[a][b], 0, 0, 0);
           }
       }
     }
@@ -357,9 +445,10 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const int j = col0 + wn + 16 * b + j_l;
+      const int jp = col0 + wn + 16 * b + j_l;   // column of the block grid
+      const int j = FOLD ? (jp < half ? 2 * jp : 2 * (jp - half) + 1) : jp;
       const int i16 = row0 + wm + 16 * a;       // n is a multiple of 32: i16 < n covers 16 rows
-      if (j >= n || i16 >= n) continue;
+      if (jp >= n || i16 >= n) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = i16 + i_base + i_step * r;
@@ -388,6 +477,9 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
 // ---------------------------------------------------------------------------------------------
 namespace {
 
+// Systems whose side is a multiple of 64 use the folded transform (their plans hold it).
+bool folded(int64_t n) { return n % 64 == 0; }
+
 struct Transform {
   double* q64 = nullptr;
   float* q32 = nullptr;
@@ -414,17 +506,29 @@ int get_transform(int64_t n, int prec, Transform* out) {
     for (int64_t k = 0; k < period; ++k) s[k] = scale * std::sin(pi * (long double)k / (n + 1));
     for (int64_t i = 0; i < n; ++i)
       for (int64_t k = 0; k < n; ++k) q[i * n + k] = (double)s[((i + 1) * (k + 1)) % period];
+    // folded systems keep rows j' of Q_{k, perm(j')}, k < n/2 (see k_pass2d); others all of Q
+    int64_t cnt = nn;
+    if (folded(n)) {
+      const int64_t K = n / 2;
+      std::vector<double> qh(n * K);
+      for (int64_t jp = 0; jp < n; ++jp) {
+        const int64_t j = jp < K ? 2 * jp : 2 * (jp - K) + 1;
+        for (int64_t k = 0; k < K; ++k) qh[jp * K + k] = q[k * n + j];
+      }
+      q.swap(qh);
+      cnt = n * K;
+    }
     if (prec == PREC_F64) {
-      if (hipMalloc(&t.q64, nn * sizeof(double)) != hipSuccess) return fail(RIDC_E_NOMEM, "Q64");
-      RIDC_HIP_TRY(hipMemcpy(t.q64, q.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+      if (hipMalloc(&t.q64, cnt * sizeof(double)) != hipSuccess) return fail(RIDC_E_NOMEM, "Q64");
+      RIDC_HIP_TRY(hipMemcpy(t.q64, q.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
     } else if (prec == PREC_F32) {
-      std::vector<float> qf(nn);
-      for (int64_t i = 0; i < nn; ++i) qf[i] = (float)q[i];
-      if (hipMalloc(&t.q32, nn * sizeof(float)) != hipSuccess) return fail(RIDC_E_NOMEM, "Q32");
-      RIDC_HIP_TRY(hipMemcpy(t.q32, qf.data(), nn * sizeof(float), hipMemcpyHostToDevice));
+      std::vector<float> qf(cnt);
+      for (int64_t i = 0; i < cnt; ++i) qf[i] = (float)q[i];
+      if (hipMalloc(&t.q32, cnt * sizeof(float)) != hipSuccess) return fail(RIDC_E_NOMEM, "Q32");
+      RIDC_HIP_TRY(hipMemcpy(t.q32, qf.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
     } else {
-      std::vector<u16> qb(2 * nn);
-      for (int64_t i = 0; i < nn; ++i) {
+      std::vector<u16> qb(2 * cnt);
+      for (int64_t i = 0; i < cnt; ++i) {
         // round to nearest even BF16 of the FP32 value, then of the FP32 remainder
         auto to_bf = [](float f) -> u16 {
           uint32_t u = __builtin_bit_cast(uint32_t, f);
@@ -436,10 +540,10 @@ int get_transform(int64_t n, int prec, Transform* out) {
         const u16 hi = to_bf(f);
         const u16 lo = to_bf(f - from_bf(hi));
         qb[i] = hi;
-        qb[nn + i] = lo;
+        qb[cnt + i] = lo;
       }
-      if (hipMalloc(&t.qbf, 2 * nn * sizeof(u16)) != hipSuccess) return fail(RIDC_E_NOMEM, "Qbf");
-      RIDC_HIP_TRY(hipMemcpy(t.qbf, qb.data(), 2 * nn * sizeof(u16), hipMemcpyHostToDevice));
+      if (hipMalloc(&t.qbf, 2 * cnt * sizeof(u16)) != hipSuccess) return fail(RIDC_E_NOMEM, "Qbf");
+      RIDC_HIP_TRY(hipMemcpy(t.qbf, qb.data(), 2 * cnt * sizeof(u16), hipMemcpyHostToDevice));
     }
   }
   *out = t;
@@ -462,7 +566,12 @@ template <int PREC, int OUT>
 void launch_pass(const Pass2D* d, const Lvl2D* lv, int count, int64_t nmax, int64_t sigma,
                  hipStream_t st) {
   const unsigned t = (unsigned)((nmax + BT - 1) / BT);
-  hipLaunchKernelGGL((k_pass2d<PREC, OUT>), dim3(t, t, count), dim3(NTHR), 0, st, d, lv, sigma);
+  if (folded(nmax))
+    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1>), dim3(t, t, count), dim3(NTHR), 0, st, d, lv,
+                       sigma);
+  else
+    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 0>), dim3(t, t, count), dim3(NTHR), 0, st, d, lv,
+                       sigma);
 }
 
 }  // namespace

@@ -167,6 +167,7 @@ class Ridc:
         self._p = make_problem(prob, dt, prec)
         self.order = self._p.order
         self.npts = self._p.n if self._p.dim == 1 else self._p.n * self._p.n
+        self.side = self._p.n
         self._h = ctypes.c_void_p()
         self._stream = stream
         _check(_lib.ridc_create(ctypes.byref(self._p), _stream_ptr(stream),
