@@ -309,8 +309,16 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-  u32x4 ra[NSPLIT][CPT], rm[NSPLIT][CPT], rb[NSPLIT][CPT];
-  auto gload = [&](int k0) {
+  // global -> register staging of one k-slice (A, its mirrored columns when folding, Q); two
+  // slices are in flight, so a slice's loads have two MFMA phases to arrive
+  struct Slice {
+    u32x4 ra[NSPLIT][CPT], rm[NSPLIT][CPT], rb[NSPLIT][CPT];
+  };
+  Slice sl0, sl1;
+  auto gload = [&](Slice& S, int k0) {
+    auto& ra = S.ra;
+    auto& rm = S.rm;
+    auto& rb = S.rb;
 #pragma unroll
     for (int s = 0; s < NSPLIT; ++s)
 #pragma unroll
@@ -327,7 +335,10 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
                           : u32x4{0, 0, 0, 0};
       }
   };
-  auto sstore = [&]() {
+  auto sstore = [&](const Slice& S) {
+    const auto& ra = S.ra;
+    const auto& rm = S.rm;
+    const auto& rb = S.rb;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int id = tid + c * NTHR;
@@ -364,12 +375,7 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   const int pa1 = FOLD && col0 + wn + 16 >= half ? 1 : 0;
   const int KT = K / BK;
   const int r16 = lane & 15;
-  gload(0);
-  for (int kt = 0; kt < KT; ++kt) {
-    __syncthreads();
-    sstore();
-    __syncthreads();
-    if (kt + 1 < KT) gload((kt + 1) * BK);
+  auto mfma_slice = [&]() {
     if constexpr (PREC == PREC_BF16) {
       // lane holds 8 consecutive k of row (l % 16), k offset 8 (l / 16)
       const int kb = (lane >> 4) * 16;                 // byte offset of the 8 k values
@@ -425,6 +431,22 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
               acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[b][a], bf[b], acc[a][b], 0, 0, 0);
           }
       }
+    }
+  };
+  gload(sl0, 0);
+  if (KT > 1) gload(sl1, BK);
+  for (int kt = 0; kt < KT; kt += 2) {
+    __syncthreads();
+    sstore(sl0);
+    __syncthreads();
+    if (kt + 2 < KT) gload(sl0, (kt + 2) * BK);
+    mfma_slice();
+    if (kt + 1 < KT) {
+      __syncthreads();
+      sstore(sl1);
+      __syncthreads();
+      if (kt + 3 < KT) gload(sl1, (kt + 3) * BK);
+      mfma_slice();
     }
   }
 
