@@ -65,6 +65,9 @@ def parse():
                     help="serving: wall-clock cap; work still queued then is reported unserved")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-check", action="store_true",
+                    help="2D: skip the FP64 reference integrations (error checks), e.g. when "
+                         "profiling")
     ap.add_argument("--reps", type=int, default=200, help="launches timed for the roofline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a float64 tensor of this many MiB three times (a plain "
@@ -91,8 +94,9 @@ def oracle_time(fn):
     return out, dt
 
 
-def run_single(args, torch, ridc, prob, u0, prec, steps, warmup, tune=True):
-    """Whole integrations of one instance; returns (seconds per integration, result, solver)."""
+def run_single(args, torch, ridc, prob, u0, prec, steps, warmup, tune=True, segments=1):
+    """Whole integrations of one instance (split into `segments` restarted RIDC runs when above
+    one); returns (seconds per integration, result, solver, initial data, tile)."""
     s = ridc.Ridc(prob, prec=prec)
     tile = None
     if prob["dim"] == 1 and args.tile:
@@ -103,13 +107,18 @@ def run_single(args, torch, ridc, prob, u0, prec, steps, warmup, tune=True):
         tile = s.autotune()
     x0 = torch.tensor(np.asarray(u0).reshape(-1), dtype=torch.float64, device="cuda")
     uT = torch.empty_like(x0)
+    def run():
+        if segments > 1:
+            s.integrate_restarts(x0, prob["nt"], segments, uT, sync=False)
+        else:
+            s.integrate(x0, prob["nt"], uT, sync=False)
     for _ in range(warmup):
-        s.integrate(x0, prob["nt"], uT, sync=False)
+        run()
     torch.cuda.synchronize()
     s.sync()
     t0 = time.perf_counter()
     for _ in range(steps):
-        s.integrate(x0, prob["nt"], uT, sync=False)
+        run()
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / steps
     s.sync()
@@ -147,6 +156,7 @@ def roofline_single(ridc, s, x0, nt, reps, bound, prec):
 
 def bench_1d(args, torch, ridc, which):
     import workloads
+    segments = 1                                        # restarted RIDC segments (section III-E)
     if which == "reacdiff1d":
         prob, u0 = workloads.config_reacdiff_1d()
         if args.nt:
@@ -157,7 +167,9 @@ def bench_1d(args, torch, ridc, which):
     elif which == "paper_advdiff":
         prob, u0 = workloads.config_paper_advdiff()
         desc = ("paper section IV-A: u_t = 0.1 u_x + 1e-3 u_xx, periodic [0,1], dx=1/1000, "
-                "first-order upwind advection, u0=2+sin 2pi x, RIDC order 4, T=40, Nt=4000, FP64")
+                "first-order upwind advection, u0=2+sin 2pi x, RIDC order 4, T=40, Nt=4000 in "
+                "10 restarted segments, FP64")
+        segments = 10
         steps, warmup = args.steps or 10, args.warmup if args.warmup is not None else 2
     elif which == "paper_burgers":
         prob, u0 = workloads.config_paper_burgers()
@@ -171,7 +183,8 @@ def bench_1d(args, torch, ridc, which):
                 "u0=sin x, RIDC order 4, T=1, Nt=200, FP64")
         steps, warmup = args.steps or 200, args.warmup if args.warmup is not None else 10
     n, nt, P = prob["n"], prob["nt"], prob["order"]
-    el, out, s, x0, tile = run_single(args, torch, ridc, prob, u0, "fp64", steps, warmup)
+    el, out, s, x0, tile = run_single(args, torch, ridc, prob, u0, "fp64", steps, warmup,
+                                      segments=segments)
     roof = roofline_single(ridc, s, x0, nt, args.reps, "hbm", "fp64")
     s.close()
     traffic = measured_traffic(which, tile)
@@ -181,18 +194,22 @@ def bench_1d(args, torch, ridc, which):
                                 "copy-calibrated; the chunk halos are re-read")
     cpu = rel = None
     if not args.no_cpu:
-        from oracle import Problem, rel_l2, ridc_pipelined
+        from oracle import Problem, rel_l2, ridc_pipelined, ridc_restarted
         reps = 20 if which == "advdiff1d" else 1
-        ref, sec = oracle_time(lambda: [ridc_pipelined(Problem.from_dict(prob), u0, nt, P)[-1]
-                                        for _ in range(reps)][-1])
+        if segments > 1:
+            ref, sec = oracle_time(lambda: ridc_restarted(Problem.from_dict(prob), u0, nt, P,
+                                                          segments))
+        else:
+            ref, sec = oracle_time(lambda: [ridc_pipelined(Problem.from_dict(prob), u0, nt, P)[-1]
+                                            for _ in range(reps)][-1])
         rel = rel_l2(out, ref)
         cpu = {"value": round(n * nt * reps / sec, 1), "unit": "grid-point-steps/s", "cores": 1,
                "kind": "oracle",
                "sample": f"the full workload {reps}x (N={n}, Nt={nt}, order {P}), {sec:.2f} s, "
                          f"one thread; host has {os.cpu_count()} logical CPUs"}
     return dict(value=n * nt / el, ms=1e3 * el, steps=steps, warmup=warmup, dtype="f64",
-                config={"workload": desc, "n": n, "nt": nt, "order": P,
-                        "pipeline_steps": nt + P * (P - 1) // 2,
+                config={"workload": desc, "n": n, "nt": nt, "order": P, "segments": segments,
+                        "pipeline_steps": nt + segments * (P * (P - 1) // 2),
                         "tile": {"threads": tile[0], "rows": tile[1], "flags": tile[2]}},
                 roofline=roof, cpu=cpu, check={"rel_l2_vs_oracle": rel})
 
@@ -200,6 +217,8 @@ def bench_1d(args, torch, ridc, which):
 def bench_2d(args, torch, ridc):
     import workloads
     prob, u0 = workloads.config_reacdiff_2d()
+    if args.nt:
+        prob = dict(prob, nt=args.nt, T=prob["T"] * args.nt / prob["nt"])
     n, nt, P = prob["n"], prob["nt"], prob["order"]
     steps, warmup = args.steps or 3, args.warmup if args.warmup is not None else 1
     el, out, s, x0, _ = run_single(args, torch, ridc, prob, u0, args.prec, steps, warmup)
@@ -216,7 +235,7 @@ def bench_2d(args, torch, ridc):
     s.close()
     check = {}
     golden = os.path.join(ROOT, "tests", "golden", "reacdiff2d_n1024_nt500.npz")
-    if os.path.exists(golden):
+    if os.path.exists(golden) and nt == 500:
         ref = np.load(golden)
         flat = out.reshape(-1)
         samp = ref["samples"][-1]
@@ -225,6 +244,8 @@ def bench_2d(args, torch, ridc):
         check["rel_l2_vs_oracle_subgrid"] = float(
             np.linalg.norm(out.reshape(n, n)[::8, ::8] - ref["top_sub8"])
             / np.linalg.norm(ref["top_sub8"]))
+    if args.no_check:
+        return finish_2d(args, prob, u0, n, nt, P, el, steps, warmup, roof, roof_rhs, check)
     # discretisation error of RIDC4 at this Nt (Richardson with an FP64 run at 2 Nt)
     prob2 = dict(prob, nt=2 * nt)
     s2 = ridc.Ridc(prob2, prec="fp64")
@@ -241,6 +262,10 @@ def bench_2d(args, torch, ridc):
         check["rel_l2_vs_fp64_gpu"] = mixed
         check["matched"] = bool(mixed <= 0.1 * err_disc)
     check["err_disc_ridc4"] = err_disc
+    return finish_2d(args, prob, u0, n, nt, P, el, steps, warmup, roof, roof_rhs, check)
+
+
+def finish_2d(args, prob, u0, n, nt, P, el, steps, warmup, roof, roof_rhs, check):
     cpu = None
     if not args.no_cpu:
         from oracle import Problem, ridc_pipelined
@@ -251,7 +276,8 @@ def bench_2d(args, torch, ridc):
                "sample": f"the full 1024^2 grid for the first {nts} time steps of all {P} levels "
                          f"({P * nts} level steps, {sec:.1f} s), one thread"}
     desc = ("2D reaction-diffusion u_t = nu Lap u + u(1-u), Dirichlet [0,1]^2, 1024x1024, "
-            f"nu=1e-4, 8 seeded bumps, RIDC order 4, T=1, Nt=500, transforms {args.prec}")
+            f"nu=1e-4, 8 seeded bumps, RIDC order 4, T={prob['T']:g}, Nt={nt}, "
+            f"transforms {args.prec}")
     return dict(value=n * n * nt / el, ms=1e3 * el, steps=steps, warmup=warmup,
                 dtype={"fp64": "f64", "fp32": "f32 transforms, f64 sums",
                        "bf16x3": "bf16x3 transforms, f64 sums"}[args.prec],
