@@ -30,25 +30,31 @@ HBM_PEAK_GBS = 8000.0                                    # MI355X HBM3E
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense matrix peaks
 METRIC = "RIDC4 grid-point-steps/s at matched L2 error vs FP64"
 
-# HBM bytes per launch of the 1D level-step kernel, from two hardware-counter runs of the same
-# workload and tile (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain
-# copy of known size: x2.0 and x1.0).  Reported only while the kernel source hashes to the one
-# that was profiled; otherwise the traffic is unknown and reported as null.
-MEASURED_TRAFFIC = {
-    ("reacdiff1d", (1024, 128, 1)): ("05ff30f0a3f112ff", 4671488),
+# HBM bytes per launch of the dominant kernels, from two hardware-counter runs of the same
+# workload and tiling (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+# plain copy of known size: x2.0 and x1.0).  Reported only while the kernel's source hashes to
+# the one that was profiled; otherwise the traffic is unknown and reported as null.
+KERNEL_SOURCE = {
+    "1d": os.path.join(ROOT, "paper_1209_4297_amd", "csrc", "kernels_1d.hip"),
+    "2d": os.path.join(ROOT, "paper_1209_4297_amd", "csrc", "kernels_2d.hip"),
 }
-KERNEL_SOURCE_1D = os.path.join(ROOT, "paper_1209_4297_amd", "csrc", "kernels_1d.hip")
+MEASURED_TRAFFIC = {
+    ("reacdiff1d", (1024, 128, 1)): ("1d", "cac06158088743f9", 4503552),
+    ("batched1d", (512, 1536)): ("1d", "cac06158088743f9", 74536141),
+    ("reacdiff2d_rhs", "fp32"): ("2d", "ca2247c75a60c5be", 193880064),
+    ("reacdiff2d", "fp32"): ("2d", "ca2247c75a60c5be", 153381888),
+}
 
 
-def measured_traffic(workload, tile):
+def measured_traffic(workload, key):
     import hashlib
-    entry = MEASURED_TRAFFIC.get((workload, tuple(tile) if tile else None))
-    if entry is None or not os.path.exists(KERNEL_SOURCE_1D):
+    entry = MEASURED_TRAFFIC.get((workload, tuple(key) if isinstance(key, (list, tuple)) else key))
+    if entry is None or not os.path.exists(KERNEL_SOURCE[entry[0]]):
         return None
-    with open(KERNEL_SOURCE_1D, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != entry[0]:
+    with open(KERNEL_SOURCE[entry[0]], "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != entry[1]:
             return None
-    return entry[1]
+    return entry[2]
 
 
 def parse():
@@ -232,6 +238,9 @@ def bench_2d(args, torch, ridc):
     roof_rhs = {"bound": "hbm", "achieved": round(ach_rhs, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach_rhs / HBM_PEAK_GBS, 5), "traffic": None,
                 "kernel": "k_rhs2d", "launch_us": round(us_rhs, 3), "bytes_per_launch": bytes_rhs}
+    if args.nt is None:
+        roof["traffic"] = measured_traffic("reacdiff2d", args.prec)
+        roof_rhs["traffic"] = measured_traffic("reacdiff2d_rhs", args.prec)
     s.close()
     check = {}
     golden = os.path.join(ROOT, "tests", "golden", "reacdiff2d_n1024_nt500.npz")
@@ -317,6 +326,11 @@ def bench_batched(args, torch, ridc):
     roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_step1d (grouped)",
             "launch_us": round(us, 3), "bytes_per_launch": bytes_per}
+    traffic = measured_traffic("batched1d", batch_tile)
+    if traffic is not None and args.nt is None:
+        roof["traffic"] = traffic
+        roof["traffic_note"] = ("HBM bytes per launch from FETCH_SIZE/WRITE_SIZE counters, "
+                                "copy-calibrated; chunk halos of the long systems are re-read")
     outs = [u.cpu().numpy() for u in uTs]
     for s in solvers:
         s.close()
