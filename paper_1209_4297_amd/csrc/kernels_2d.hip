@@ -28,6 +28,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "ridc2d.h"
 #include "ridc_internal.h"
@@ -451,7 +452,15 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   }
 
   // epilogue: acc[a][b] holds C[i][j] for the 16 x 16 tile at rows row0 + wm + 16a, columns
-  // col0 + wn + 16b (column l%16 of lane l); the pass stores the transpose, out[j][i]
+  // col0 + wn + 16b (column l%16 of lane l); the pass stores the transpose, out[j][i].  The tile
+  // goes through LDS (the A staging area) RJ output rows at a time, so that each thread then
+  // finishes and writes a contiguous run of ET elements of one output row.
+  typedef typename std::conditional<PREC == PREC_F64, double, float>::type ST;
+  constexpr int RJ = PREC == PREC_F64 ? 16 : 32;              // output rows per round
+  constexpr int SS = BT + 16 / (int)sizeof(ST);               // LDS row stride, 16-byte rows
+  constexpr int ET = RJ * BT / NTHR;                          // elements per thread: 4 or 8
+  static_assert(RJ * SS * sizeof(ST) <= sizeof(As[0]), "staging fits the A buffer");
+  ST* stg = reinterpret_cast<ST*>(&As[0][0][0]);
   double* out64 = nullptr;
   const double* base = nullptr;
   if constexpr (OUT == OUT_FINAL) {
@@ -463,35 +472,65 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   const int i_base = PREC == PREC_F64 ? (lane >> 4) : 4 * (lane >> 4);
   constexpr int i_step = PREC == PREC_F64 ? 4 : 1;
   const int j_l = lane & 15;
+  const int orow = tid / (BT / ET);                   // this thread's output row in a round
+  const int oc = (tid % (BT / ET)) * ET;              // and its first element
+  for (int jr = 0; jr < BT; jr += RJ) {
+    __syncthreads();                                  // the buffer is free
+    if (wn <= jr && jr < wn + 32) {                   // this wave holds rows jr .. jr + RJ
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const int jl0 = wn + 16 * b;
+        if (jl0 < jr || jl0 >= jr + RJ) continue;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int jp = col0 + wn + 16 * b + j_l;   // column of the block grid
-      const int j = FOLD ? (jp < half ? 2 * jp : 2 * (jp - half) + 1) : jp;
-      const int i16 = row0 + wm + 16 * a;       // n is a multiple of 32: i16 < n covers 16 rows
-      if (jp >= n || i16 >= n) continue;
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i16 + i_base + i_step * r;
-        const int64_t o = (int64_t)j * n + i;
-        double v = (double)acc[a][b][r];
-        if (E.divide) v = v / (1.0 + (E.lam[i] + E.lam[j]));
-        if constexpr (OUT == OUT_F64) {
-          ((double*)E.C)[o] = v;
-        } else if constexpr (OUT == OUT_F32) {
-          ((float*)E.C)[o] = (float)v;
-        } else if constexpr (OUT == OUT_BF16) {
-          u16 h, l;
-          split_bf16(v, &h, &l);
-          ((u16*)E.C)[o] = h;
-          ((u16*)E.C)[nn + o] = l;
-        } else {
-          const double add = E.add ? E.add[o] : 0.0;
-          out64[o] = base[o] + (add + v);
-        }
+          for (int r = 0; r < 4; ++r)
+            stg[(jl0 - jr + j_l) * SS + wm + 16 * a + i_base + i_step * r] = (ST)acc[a][b][r];
       }
     }
+    __syncthreads();
+    const int jp = col0 + jr + orow;                  // column of the block grid
+    const int i0 = row0 + oc;
+    if (jp >= n || i0 >= n) continue;                 // n is a multiple of 32: whole runs
+    const int j = FOLD ? (jp < half ? 2 * jp : 2 * (jp - half) + 1) : jp;
+    const int64_t o = (int64_t)j * n + i0;
+    double v[ET];
+#pragma unroll
+    for (int e = 0; e < ET; ++e) v[e] = (double)stg[orow * SS + oc + e];
+    if (E.divide) {
+      const double lj = E.lam[j];
+#pragma unroll
+      for (int e = 0; e < ET; ++e) v[e] = v[e] / (1.0 + (E.lam[i0 + e] + lj));
+    }
+    if constexpr (OUT == OUT_F64) {
+#pragma unroll
+      for (int e = 0; e < ET; e += 2) *(dbl2*)((double*)E.C + o + e) = dbl2{v[e], v[e + 1]};
+    } else if constexpr (OUT == OUT_F32) {
+#pragma unroll
+      for (int e = 0; e < ET; e += 4)
+        *(flt4*)((float*)E.C + o + e) =
+            flt4{(float)v[e], (float)v[e + 1], (float)v[e + 2], (float)v[e + 3]};
+    } else if constexpr (OUT == OUT_BF16) {
+      static_assert(ET == 8, "BF16 runs are 16 bytes");
+      u16x8 hv, lv;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        u16 h, l;
+        split_bf16(v[e], &h, &l);
+        hv[e] = h;
+        lv[e] = l;
+      }
+      *(u16x8*)((u16*)E.C + o) = hv;
+      *(u16x8*)((u16*)E.C + nn + o) = lv;
+    } else {
+#pragma unroll
+      for (int e = 0; e < ET; e += 2) {
+        const dbl2 bs = *(const dbl2*)(base + o + e);
+        const dbl2 ad = E.add ? *(const dbl2*)(E.add + o + e) : dbl2{0.0, 0.0};
+        *(dbl2*)(out64 + o + e) = dbl2{bs[0] + (ad[0] + v[e]), bs[1] + (ad[1] + v[e + 1])};
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
