@@ -283,13 +283,28 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   __shared__ __attribute__((aligned(16))) T As[NA][NSPLIT][BT * LDE];
   __shared__ __attribute__((aligned(16))) T Bs[NSPLIT][BT * LDE];
 
-  const Pass2D& E = passes[blockIdx.z];
+  // XCD-aware tile order: workgroups go to the 8 XCDs round-robin by linear id, so tile q of
+  // XCD x is x * (T / 8) + (id / 8): each XCD takes a contiguous run of tiles, and the column
+  // tiles of one row tile of A meet in one L2 (identity when T is not a multiple of 8)
+  unsigned bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  {
+    const unsigned t = gridDim.x;
+    const unsigned T = t * gridDim.y * gridDim.z;
+    const unsigned id = bx + t * (by + gridDim.y * bz);
+    if (T % 8 == 0) {
+      const unsigned q = (id % 8) * (T / 8) + id / 8;
+      bx = q % t;
+      by = (q / t) % gridDim.y;
+      bz = q / (t * gridDim.y);
+    }
+  }
+  const Pass2D& E = passes[bz];
   const Lvl2D& L = levels[E.level];
   int64_t m;
   if (!level_active(L, sigma, &m)) return;
   const int n = L.n;
-  const int row0 = blockIdx.y * BT;          // rows of A (i)
-  const int col0 = blockIdx.x * BT;          // columns of Q (j)
+  const int row0 = by * BT;                  // rows of A (i)
+  const int col0 = bx * BT;                  // columns of Q (j)
   if (row0 >= n || col0 >= n) return;
   const int64_t nn = (int64_t)n * n;
   const T* A = (const T*)E.A;
