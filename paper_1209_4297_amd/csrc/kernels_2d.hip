@@ -241,6 +241,18 @@ __device__ __forceinline__ void fold_f32(u32x4 a, u32x4 m, u32x4* sum, u32x4* di
 __device__ __forceinline__ float bf_to_f(unsigned short b) {
   return __builtin_bit_cast(float, (unsigned int)b << 16);
 }
+// only the sums (sg = 1) or only the differences (sg = -1), for blocks whose output columns all
+// have one parity
+__device__ __forceinline__ u32x4 fold1_f64(u32x4 a, u32x4 m, double sg) {
+  const dbl2 x = __builtin_bit_cast(dbl2, a), y = __builtin_bit_cast(dbl2, m);
+  return __builtin_bit_cast(u32x4, dbl2{x[0] + sg * y[1], x[1] + sg * y[0]});
+}
+__device__ __forceinline__ u32x4 fold1_f32(u32x4 a, u32x4 m, float sg) {
+  const flt4 x = __builtin_bit_cast(flt4, a), y = __builtin_bit_cast(flt4, m);
+  return __builtin_bit_cast(u32x4, flt4{x[0] + sg * y[3], x[1] + sg * y[2], x[2] + sg * y[1],
+                                        x[3] + sg * y[0]});
+}
+
 // split BF16 operands (hi, lo): the folded values are formed in FP32 and split again
 __device__ __forceinline__ void fold_bf16(u32x4 ah, u32x4 al, u32x4 mh, u32x4 ml, u32x4* sh,
                                           u32x4* sl, u32x4* dh, u32x4* dl) {
@@ -262,6 +274,23 @@ __device__ __forceinline__ void fold_bf16(u32x4 ah, u32x4 al, u32x4 mh, u32x4 ml
   *sl = __builtin_bit_cast(u32x4, osl);
   *dh = __builtin_bit_cast(u32x4, odh);
   *dl = __builtin_bit_cast(u32x4, odl);
+}
+__device__ __forceinline__ void fold1_bf16(u32x4 ah, u32x4 al, u32x4 mh, u32x4 ml, float sg,
+                                           u32x4* oh, u32x4* ol) {
+  const u16x8 xh = __builtin_bit_cast(u16x8, ah), xl = __builtin_bit_cast(u16x8, al);
+  const u16x8 yh = __builtin_bit_cast(u16x8, mh), yl = __builtin_bit_cast(u16x8, ml);
+  u16x8 h8, l8;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float x = bf_to_f(xh[e]) + bf_to_f(xl[e]);
+    const float y = bf_to_f(yh[7 - e]) + bf_to_f(yl[7 - e]);
+    const float v = x + sg * y;
+    const __bf16 vh = (__bf16)v;
+    h8[e] = __builtin_bit_cast(unsigned short, vh);
+    l8[e] = __builtin_bit_cast(unsigned short, (__bf16)(v - (float)vh));
+  }
+  *oh = __builtin_bit_cast(u32x4, h8);
+  *ol = __builtin_bit_cast(u32x4, l8);
 }
 
 // FOLD (n a multiple of 64): the contraction runs over k < n/2 with the folded A operands and
@@ -351,6 +380,10 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
                           : u32x4{0, 0, 0, 0};
       }
   };
+  // a block whose output columns all lie on one side of n/2 needs only the sums (side 0) or
+  // only the differences (side 1)
+  const bool one_side = FOLD && (col0 + BT <= (n >> 1) || col0 >= (n >> 1));
+  const int side = FOLD && col0 >= (n >> 1) ? 1 : 0;
   auto sstore = [&](const Slice& S) {
     const auto& ra = S.ra;
     const auto& rm = S.rm;
@@ -364,12 +397,26 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
 #pragma unroll
         for (int s = 0; s < NSPLIT; ++s) *(u32x4*)((char*)As[0][s] + off) = ra[s][c];
       } else if constexpr (PREC == PREC_BF16) {
-        u32x4 sh, sl, dh, dl;
-        fold_bf16(ra[0][c], ra[1][c], rm[0][c], rm[1][c], &sh, &sl, &dh, &dl);
-        *(u32x4*)((char*)As[0][0] + off) = sh;
-        *(u32x4*)((char*)As[0][1] + off) = sl;
-        *(u32x4*)((char*)As[1][0] + off) = dh;
-        *(u32x4*)((char*)As[1][1] + off) = dl;
+        if (one_side) {
+          u32x4 oh, ol;
+          fold1_bf16(ra[0][c], ra[1][c], rm[0][c], rm[1][c], side ? -1.0f : 1.0f, &oh, &ol);
+          *(u32x4*)((char*)As[side][0] + off) = oh;
+          *(u32x4*)((char*)As[side][1] + off) = ol;
+        } else {
+          u32x4 sh, sl, dh, dl;
+          fold_bf16(ra[0][c], ra[1][c], rm[0][c], rm[1][c], &sh, &sl, &dh, &dl);
+          *(u32x4*)((char*)As[0][0] + off) = sh;
+          *(u32x4*)((char*)As[0][1] + off) = sl;
+          *(u32x4*)((char*)As[1][0] + off) = dh;
+          *(u32x4*)((char*)As[1][1] + off) = dl;
+        }
+      } else if (one_side) {
+        if constexpr (PREC == PREC_F64)
+          *(u32x4*)((char*)As[side][0] + off) =
+              fold1_f64(ra[0][c], rm[0][c], side ? -1.0 : 1.0);
+        else
+          *(u32x4*)((char*)As[side][0] + off) =
+              fold1_f32(ra[0][c], rm[0][c], side ? -1.0f : 1.0f);
       } else {
         u32x4 su, di;
         if constexpr (PREC == PREC_F64)
