@@ -41,8 +41,10 @@ KERNEL_SOURCE = {
 MEASURED_TRAFFIC = {
     ("reacdiff1d", (1024, 128, 1)): ("1d", "cac06158088743f9", 4503552),
     ("batched1d", (512, 1536)): ("1d", "cac06158088743f9", 74536141),
-    ("reacdiff2d_rhs", "fp32"): ("2d", "ca2247c75a60c5be", 193880064),
-    ("reacdiff2d", "fp32"): ("2d", "ca2247c75a60c5be", 153381888),
+    ("reacdiff2d_rhs", "fp32"): ("2d", "44a0b267f16a84bf", 193865318),
+    ("reacdiff2d", "fp32"): ("2d", "44a0b267f16a84bf", 50599731),
+    ("reacdiff2d_rhs", "bf16x3"): ("2d", "44a0b267f16a84bf", 193842176),
+    ("reacdiff2d", "bf16x3"): ("2d", "44a0b267f16a84bf", 50627379),
 }
 
 
