@@ -536,7 +536,25 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   const int j_l = lane & 15;
   const int orow = tid / (BT / ET);                   // this thread's output row in a round
   const int oc = (tid % (BT / ET)) * ET;              // and its first element
+  // the final update's FP64 operands (base, add) of this thread's run, loaded one round ahead
+  dbl2 bq[2][ET / 2], aq[2][ET / 2];
+  auto fetch = [&](int jr, int slot) {
+    if constexpr (OUT == OUT_FINAL) {
+      const int jp = col0 + jr + orow;
+      const int i0 = row0 + oc;
+      if (jp >= n || i0 >= n) return;
+      const int j = FOLD ? (jp < half ? 2 * jp : 2 * (jp - half) + 1) : jp;
+      const int64_t o = (int64_t)j * n + i0;
+#pragma unroll
+      for (int e = 0; e < ET / 2; ++e) {
+        bq[slot][e] = *(const dbl2*)(base + o + 2 * e);
+        aq[slot][e] = E.add ? *(const dbl2*)(E.add + o + 2 * e) : dbl2{0.0, 0.0};
+      }
+    }
+  };
+  fetch(0, 0);
   for (int jr = 0; jr < BT; jr += RJ) {
+    const int cur = (jr / RJ) & 1;
     __syncthreads();                                  // the buffer is free
     if (wn <= jr && jr < wn + 32) {                   // this wave holds rows jr .. jr + RJ
 #pragma unroll
@@ -551,6 +569,7 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       }
     }
     __syncthreads();
+    if (jr + RJ < BT) fetch(jr + RJ, cur ^ 1);
     const int jp = col0 + jr + orow;                  // column of the block grid
     const int i0 = row0 + oc;
     if (jp >= n || i0 >= n) continue;                 // n is a multiple of 32: whole runs
@@ -587,8 +606,8 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
     } else {
 #pragma unroll
       for (int e = 0; e < ET; e += 2) {
-        const dbl2 bs = *(const dbl2*)(base + o + e);
-        const dbl2 ad = E.add ? *(const dbl2*)(E.add + o + e) : dbl2{0.0, 0.0};
+        const dbl2 bs = bq[cur][e / 2];
+        const dbl2 ad = aq[cur][e / 2];
         *(dbl2*)(out64 + o + e) = dbl2{bs[0] + (ad[0] + v[e]), bs[1] + (ad[1] + v[e + 1])};
       }
     }
