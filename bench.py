@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--workload", default="reacdiff1d",
                     choices=["reacdiff1d", "advdiff1d", "reacdiff2d", "batched1d", "serving",
                              "paper_advdiff", "paper_burgers"])
+    ap.add_argument("--rate", type=float, default=200.0,
+                    help="serving: Poisson arrival rate in requests/s (the configured load is 200)")
     ap.add_argument("--horizon", type=float, default=10.0,
                     help="serving: seconds of Poisson arrivals admitted")
     ap.add_argument("--max-wall", type=float, default=40.0,
@@ -365,7 +367,7 @@ def bench_serving(args, torch, ridc):
     Nt 100..500, split-BF16 or FP32 transforms with FP64 refinement), continuous batching."""
     import workloads
     from paper_1209_4297_amd.serve import GpuExecutor, Request, Server
-    arrivals = workloads.serving_requests(duration=args.horizon)
+    arrivals = workloads.serving_requests(rate=args.rate, duration=args.horizon)
     reqs = []
     for i, a in enumerate(arrivals):
         n = a["prob"]["n"]
@@ -396,8 +398,9 @@ def bench_serving(args, torch, ridc):
         sv.close()
         check["checked"] += 1
         check["solo_bitwise_equal"] &= bool(torch.equal(alone, r.result))
-    desc = ("serving: Poisson 200 req/s 2D reaction-diffusion, side U{128,256,512,1024}, order "
-            "U{2,3,4}, nu logU(1e-5,1e-3), Nt U{100..500}, T=1, seeded bumps, transforms "
+    desc = (f"serving: Poisson {args.rate:g} req/s 2D reaction-diffusion, side "
+            "U{128,256,512,1024}, order U{2,3,4}, nu logU(1e-5,1e-3), Nt U{100..500}, T=1, "
+            "seeded bumps, transforms "
             f"{reqs[0].prec} + FP64 refinement; arrivals for {args.horizon:.0f} s")
     roof = None
     return dict(value=stats["completed_grid_point_steps_per_s"], ms=1e3 * stats["wall_s"],
