@@ -296,21 +296,34 @@ __device__ __forceinline__ void fold1_bf16(u32x4 ah, u32x4 al, u32x4 mh, u32x4 m
 // FOLD (n a multiple of 64): the contraction runs over k < n/2 with the folded A operands and
 // E.Q the folded transform: row j' (n rows) holds Q_{k, perm(j')} for k < n/2, perm(j') = 2j'
 // for j' < n/2 and 2(j' - n/2) + 1 above; output column j' of the block grid is column perm(j').
-template <int PREC, int OUT, int FOLD>
+// KX = 2 doubles the k-slice (one slice in flight instead of two); the operands then need more
+// than 64 KB of LDS, so every variant takes its LDS dynamically (pass_lds_bytes).
+template <int PREC, int KX>
+constexpr size_t pass_lds_bytes(int fold) {
+  typedef typename Tr<PREC>::T T;
+  constexpr int BK = Tr<PREC>::BK * KX;
+  constexpr int LDE = (BK * (int)sizeof(T) + 16) / (int)sizeof(T);
+  constexpr int NSPLIT = PREC == PREC_BF16 ? 2 : 1;
+  return (size_t)((fold ? 2 : 1) * NSPLIT + NSPLIT) * BT * LDE * sizeof(T);
+}
+
+template <int PREC, int OUT, int FOLD, int KX>
 __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ passes,
                                                  const Lvl2D* __restrict__ levels, int64_t sigma) {
   typedef Tr<PREC> TR;
   typedef typename TR::T T;
   typedef typename TR::Acc Acc;
-  constexpr int BK = TR::BK;
+  constexpr int BK = TR::BK * KX;
   constexpr int ROWB = BK * (int)sizeof(T) + 16;     // LDS row stride in bytes (16-aligned)
   constexpr int LDE = ROWB / (int)sizeof(T);          // ... in elements
   constexpr int CH = BK * (int)sizeof(T) / 16;        // 16-byte chunks per row
   constexpr int NSPLIT = PREC == PREC_BF16 ? 2 : 1;
   constexpr int CPT = BT * CH / NTHR;                 // chunks per thread per operand and split
   constexpr int NA = FOLD ? 2 : 1;                    // A operands: (folded sums, differences)
-  __shared__ __attribute__((aligned(16))) T As[NA][NSPLIT][BT * LDE];
-  __shared__ __attribute__((aligned(16))) T Bs[NSPLIT][BT * LDE];
+  extern __shared__ __attribute__((aligned(16))) unsigned char pass_smem[];
+  T (*As)[NSPLIT][BT * LDE] = reinterpret_cast<T (*)[NSPLIT][BT * LDE]>(pass_smem);
+  T (*Bs)[BT * LDE] =
+      reinterpret_cast<T (*)[BT * LDE]>(pass_smem + (size_t)NA * NSPLIT * BT * LDE * sizeof(T));
 
   // XCD-aware tile order: workgroups go to the 8 XCDs round-robin by linear id, so tile q of
   // XCD x is x * (T / 8) + (id / 8): each XCD takes a contiguous run of tiles, and the column
@@ -318,10 +331,10 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   unsigned bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
   {
     const unsigned t = gridDim.x;
-    const unsigned T = t * gridDim.y * gridDim.z;
+    const unsigned tiles = t * gridDim.y * gridDim.z;
     const unsigned id = bx + t * (by + gridDim.y * bz);
-    if (T % 8 == 0) {
-      const unsigned q = (id % 8) * (T / 8) + id / 8;
+    if (tiles % 8 == 0) {
+      const unsigned q = (id % 8) * (tiles / 8) + id / 8;
       bx = q % t;
       by = (q / t) % gridDim.y;
       bz = q / (t * gridDim.y);
@@ -440,8 +453,10 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   const int r16 = lane & 15;
   auto mfma_slice = [&]() {
     if constexpr (PREC == PREC_BF16) {
-      // lane holds 8 consecutive k of row (l % 16), k offset 8 (l / 16)
-      const int kb = (lane >> 4) * 16;                 // byte offset of the 8 k values
+#pragma unroll
+    for (int ks = 0; ks < KX; ++ks) {
+      // lane holds 8 consecutive k of row (l % 16), k offset 8 (l / 16), of k-step ks of 32
+      const int kb = (lane >> 4) * 16 + ks * 64;       // byte offset of the 8 k values
       bf16x8 ahi[2][4], alo[2][4], bhi[2], blo[2];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -470,6 +485,7 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[b][a], blo[b], acc[a][b], 0, 0, 0);
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[b][a], bhi[b], acc[a][b], 0, 0, 0);
         }
+    }
     } else {
       // k-steps of 4: lane holds element (row l % 16, k l / 16)
       const int k4 = lane >> 4;
@@ -496,19 +512,31 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       }
     }
   };
-  gload(sl0, 0);
-  if (KT > 1) gload(sl1, BK);
-  for (int kt = 0; kt < KT; kt += 2) {
-    __syncthreads();
-    sstore(sl0);
-    __syncthreads();
-    if (kt + 2 < KT) gload(sl0, (kt + 2) * BK);
-    mfma_slice();
-    if (kt + 1 < KT) {
+  if constexpr (KX == 1) {
+    gload(sl0, 0);
+    if (KT > 1) gload(sl1, BK);
+    for (int kt = 0; kt < KT; kt += 2) {
       __syncthreads();
-      sstore(sl1);
+      sstore(sl0);
       __syncthreads();
-      if (kt + 3 < KT) gload(sl1, (kt + 3) * BK);
+      if (kt + 2 < KT) gload(sl0, (kt + 2) * BK);
+      mfma_slice();
+      if (kt + 1 < KT) {
+        __syncthreads();
+        sstore(sl1);
+        __syncthreads();
+        if (kt + 3 < KT) gload(sl1, (kt + 3) * BK);
+        mfma_slice();
+      }
+    }
+  } else {
+    // wide slices: one in flight, its loads cover a whole MFMA phase of twice the length
+    gload(sl0, 0);
+    for (int kt = 0; kt < KT; ++kt) {
+      __syncthreads();
+      sstore(sl0);
+      __syncthreads();
+      if (kt + 1 < KT) gload(sl0, (kt + 1) * BK);
       mfma_slice();
     }
   }
@@ -704,16 +732,50 @@ size_t level_ws_bytes(int64_t n, int prec) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Wide k-slices for the split-BF16 pass when the folded contraction is a multiple of twice the
+// slice (measured: 31.9 -> 29.2 us per pass at 1024^2; the FP32 and FP64 passes gain nothing).
+template <int PREC>
+bool wide_slices(int64_t n) {
+  return PREC == PREC_BF16 && folded(n) && (n / 2) % (2 * Tr<PREC>::BK) == 0;
+}
+
 template <int PREC, int OUT>
 void launch_pass(const Pass2D* d, const Lvl2D* lv, int count, int64_t nmax, int64_t sigma,
                  hipStream_t st) {
   const unsigned t = (unsigned)((nmax + BT - 1) / BT);
-  if (folded(nmax))
-    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1>), dim3(t, t, count), dim3(NTHR), 0, st, d, lv,
-                       sigma);
-  else
-    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 0>), dim3(t, t, count), dim3(NTHR), 0, st, d, lv,
-                       sigma);
+  const dim3 grid(t, t, count);
+  const size_t full = pass_lds_bytes<PREC, 1>(0), fold = pass_lds_bytes<PREC, 1>(1);
+  const size_t wide = pass_lds_bytes<PREC, 2>(1);
+  if (!folded(nmax)) {
+    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 0, 1>), grid, dim3(NTHR), full, st, d, lv, sigma);
+  } else if (!wide_slices<PREC>(nmax)) {
+    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 1>), grid, dim3(NTHR), fold, st, d, lv, sigma);
+  } else {
+    if constexpr (PREC == PREC_BF16)
+      hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 2>), grid, dim3(NTHR), wide, st, d, lv, sigma);
+  }
+}
+
+// Allow the wide-slice variants their LDS (host call, outside any stream capture).
+template <int PREC, int OUT>
+hipError_t allow_wide_out() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass2d<PREC, OUT, 1, 2>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)pass_lds_bytes<PREC, 2>(1));
+}
+
+// the outputs each precision's passes use: its own type, the FP64 first solve, the final update
+template <int PREC>
+hipError_t allow_wide() {
+  constexpr int OWN = PREC == PREC_F64 ? OUT_F64 : (PREC == PREC_F32 ? OUT_F32 : OUT_BF16);
+  hipError_t e = allow_wide_out<PREC, OWN>();
+  if (e == hipSuccess && OWN != OUT_F64) e = allow_wide_out<PREC, OUT_F64>();
+  if (e == hipSuccess) e = allow_wide_out<PREC, OUT_FINAL>();
+  return e;
+}
+
+hipError_t prepare_pass_kernels(int prec) {
+  return prec == PREC_BF16 ? allow_wide<PREC_BF16>() : hipSuccess;
 }
 
 }  // namespace
@@ -750,6 +812,8 @@ int plan2d_create(const ridc_problem* p, double h, double* const* ring, const in
   const int64_t n = p->n, nn = n * n;
   Transform tf;
   int rc = get_transform(n, pl->prec, &tf);
+  if (rc == RIDC_OK && prepare_pass_kernels(pl->prec) != hipSuccess)
+    rc = fail(RIDC_E_HIP, "wide-slice transform kernels need more LDS than the device allows");
   if (rc != RIDC_OK) {
     delete pl;
     return rc;
