@@ -656,11 +656,10 @@ int arm_handle(ridc_handle* h, const double* u0_dev, int64_t nsteps) {
   return plan2d_arm(h->p2, nsteps, h->stream);
 }
 
-// Run a list of vector copies (optionally checking the copied values) as one launch, the list
-// going through the batch arena's pinned staging.
+// Run a list of vector copies (optionally checking the copied values), the list going through
+// the batch arena's pinned staging; one launch per 65535 items (the grid's y extent).
 int stage_copies(const std::vector<CopyItem>& c, hipStream_t stream) {
   if (c.empty()) return RIDC_OK;
-  if (c.size() > 65535) return fail(RIDC_E_INVAL, "too many instances in one batch");
   int rc = arena_reserve(0, 0);
   if (rc != RIDC_OK) return rc;
   if (c.size() > g_arena.cap_copy) {
@@ -684,7 +683,10 @@ int stage_copies(const std::vector<CopyItem>& c, hipStream_t stream) {
                               hipMemcpyHostToDevice, stream));
   RIDC_HIP_TRY(hipEventRecord(g_arena.done, stream));
   g_arena.pending = true;
-  RIDC_HIP_TRY(launch_copy_items(g_arena.d_copy, (int)c.size(), most, stream));
+  for (size_t off = 0; off < c.size(); off += 65535) {
+    const int cnt = (int)std::min<size_t>(65535, c.size() - off);
+    RIDC_HIP_TRY(launch_copy_items(g_arena.d_copy + off, cnt, most, stream));
+  }
   return RIDC_OK;
 }
 

@@ -397,6 +397,26 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   // only the differences (side 1)
   const bool one_side = FOLD && (col0 + BT <= (n >> 1) || col0 >= (n >> 1));
   const int side = FOLD && col0 >= (n >> 1) ? 1 : 0;
+  // FP32/FP64 operand rows keep a k-slice permuted, k at (k % 4) * KQ + k / 4, so that the KQ
+  // values one lane consumes over the slice (k = 4i + lane/16) are contiguous; BF16 rows keep
+  // k in order (its instruction takes 8 consecutive k per lane).
+  constexpr int KQ = BK / 4;
+  auto put = [&](T* row_base, int q, u32x4 v) {
+    if constexpr (PREC == PREC_BF16) {
+      *(u32x4*)((char*)row_base + q * 16) = v;
+    } else {
+      constexpr int EV = 16 / (int)sizeof(T);
+      struct Ev {
+        T x[EV];
+      };
+      const Ev ev = __builtin_bit_cast(Ev, v);
+#pragma unroll
+      for (int e = 0; e < EV; ++e) {
+        const int k = q * EV + e;
+        row_base[(k & 3) * KQ + (k >> 2)] = ev.x[e];
+      }
+    }
+  };
   auto sstore = [&](const Slice& S) {
     const auto& ra = S.ra;
     const auto& rm = S.rm;
@@ -405,42 +425,40 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
     for (int c = 0; c < CPT; ++c) {
       const int id = tid + c * NTHR;
       const int r = id / CH, q = id % CH;
-      const int off = r * ROWB + q * 16;
+      const int ro = r * LDE;                        // row start, in elements
       if constexpr (!FOLD) {
 #pragma unroll
-        for (int s = 0; s < NSPLIT; ++s) *(u32x4*)((char*)As[0][s] + off) = ra[s][c];
+        for (int s = 0; s < NSPLIT; ++s) put(As[0][s] + ro, q, ra[s][c]);
       } else if constexpr (PREC == PREC_BF16) {
         if (one_side) {
           u32x4 oh, ol;
           fold1_bf16(ra[0][c], ra[1][c], rm[0][c], rm[1][c], side ? -1.0f : 1.0f, &oh, &ol);
-          *(u32x4*)((char*)As[side][0] + off) = oh;
-          *(u32x4*)((char*)As[side][1] + off) = ol;
+          put(As[side][0] + ro, q, oh);
+          put(As[side][1] + ro, q, ol);
         } else {
           u32x4 sh, sl, dh, dl;
           fold_bf16(ra[0][c], ra[1][c], rm[0][c], rm[1][c], &sh, &sl, &dh, &dl);
-          *(u32x4*)((char*)As[0][0] + off) = sh;
-          *(u32x4*)((char*)As[0][1] + off) = sl;
-          *(u32x4*)((char*)As[1][0] + off) = dh;
-          *(u32x4*)((char*)As[1][1] + off) = dl;
+          put(As[0][0] + ro, q, sh);
+          put(As[0][1] + ro, q, sl);
+          put(As[1][0] + ro, q, dh);
+          put(As[1][1] + ro, q, dl);
         }
       } else if (one_side) {
         if constexpr (PREC == PREC_F64)
-          *(u32x4*)((char*)As[side][0] + off) =
-              fold1_f64(ra[0][c], rm[0][c], side ? -1.0 : 1.0);
+          put(As[side][0] + ro, q, fold1_f64(ra[0][c], rm[0][c], side ? -1.0 : 1.0));
         else
-          *(u32x4*)((char*)As[side][0] + off) =
-              fold1_f32(ra[0][c], rm[0][c], side ? -1.0f : 1.0f);
+          put(As[side][0] + ro, q, fold1_f32(ra[0][c], rm[0][c], side ? -1.0f : 1.0f));
       } else {
         u32x4 su, di;
         if constexpr (PREC == PREC_F64)
           fold_f64(ra[0][c], rm[0][c], &su, &di);
         else
           fold_f32(ra[0][c], rm[0][c], &su, &di);
-        *(u32x4*)((char*)As[0][0] + off) = su;
-        *(u32x4*)((char*)As[1][0] + off) = di;
+        put(As[0][0] + ro, q, su);
+        put(As[1][0] + ro, q, di);
       }
 #pragma unroll
-      for (int s = 0; s < NSPLIT; ++s) *(u32x4*)((char*)Bs[s] + off) = rb[s][c];
+      for (int s = 0; s < NSPLIT; ++s) put(Bs[s] + ro, q, rb[s][c]);
     }
   };
 
@@ -487,29 +505,49 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
         }
     }
     } else {
-      // k-steps of 4: lane holds element (row l % 16, k l / 16)
+      // k-steps of 4: lane holds element (row l % 16, k 4i + l / 16) of step i; its KQ values
+      // of the slice are contiguous in the permuted rows, read 16 bytes at a time
       const int k4 = lane >> 4;
+      constexpr int EV = 16 / (int)sizeof(T);
+      struct Frag {
+        T x[KQ];
+      };
+      auto frag = [&](const T* row) {
+        Frag f;
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        T af[2][4], bf[2];
+        for (int v = 0; v < KQ / EV; ++v) {
+          const u32x4 w = *(const u32x4*)(row + k4 * KQ + v * EV);
+          struct Ev {
+            T x[EV];
+          };
+          const Ev ev = __builtin_bit_cast(Ev, w);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int ai = (wm + t * 16 + r16) * LDE + kk + k4;
-          af[0][t] = As[pa0][0][ai];
-          af[1][t] = pa1 != pa0 ? As[pa1][0][ai] : af[0][t];
+          for (int e = 0; e < EV; ++e) f.x[v * EV + e] = ev.x[e];
         }
+        return f;
+      };
+      Frag af[2][4], bf[2];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) bf[t] = Bs[0][(wn + t * 16 + r16) * LDE + kk + k4];
+      for (int t = 0; t < 4; ++t) {
+        const int ro = (wm + t * 16 + r16) * LDE;
+        af[0][t] = frag(As[pa0][0] + ro);
+        af[1][t] = pa1 != pa0 ? frag(As[pa1][0] + ro) : af[0][t];
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) bf[t] = frag(Bs[0] + (wn + t * 16 + r16) * LDE);
+#pragma unroll
+      for (int i = 0; i < KQ; ++i)
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
             if constexpr (PREC == PREC_F64)
-              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[b][a], bf[b], acc[a][b], 0, 0, 0);
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[b][a].x[i], bf[b].x[i],
+                                                               acc[a][b], 0, 0, 0);
             else
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[b][a], bf[b], acc[a][b], 0, 0, 0);
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[b][a].x[i], bf[b].x[i],
+                                                               acc[a][b], 0, 0, 0);
           }
-      }
     }
   };
   if constexpr (KX == 1) {
