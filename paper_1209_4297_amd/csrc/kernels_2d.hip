@@ -41,7 +41,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
-enum { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16 = 2, OUT_FINAL = 3 };
+enum { OUT_F64 = 0, OUT_F32 = 1, OUT_FINAL = 3 };
 
 // One (instance, level) of the 2D pipeline: static for a handle.
 struct Lvl2D {
@@ -50,7 +50,7 @@ struct Lvl2D {
   const double* W;      // weights, j rows x (j+1)
   double* b64;          // FP64 right-hand side (kept for the residual)
   double* x64;          // FP64 first solve (refinement) or FP64 intermediate
-  void* lo0;            // low-precision buffers (FP32, or BF16 hi then lo)
+  void* lo0;            // FP32 buffers of the reduced-precision paths
   void* lo1;
   int64_t nt, sigma0;
   int32_t n, j, R_own, R_prev, fe, prec;
@@ -59,7 +59,7 @@ struct Lvl2D {
 
 // One batch entry of a transform pass.
 struct Pass2D {
-  const void* A;        // input, row-major n x n (FP64, FP32, or BF16 hi; lo follows at +n*n)
+  const void* A;        // input, row-major n x n (FP64, or FP32 in the reduced-precision paths)
   void* C;              // output (unless final)
   const double* add;    // final epilogue: extra FP64 term (x1 of the refinement), nullable
   const void* Q;        // transform matrix in the input precision (BF16: hi, lo at +n*n)
@@ -109,24 +109,10 @@ __device__ __forceinline__ double lap5(const double* __restrict__ v, int iy, int
   return ((w + e) + (s + no)) - 4.0 * v[c];
 }
 
-__device__ __forceinline__ void split_bf16(double x, u16* hi, u16* lo) {
-  const float xf = (float)x;
-  const __bf16 h = (__bf16)xf;
-  const float r = xf - (float)h;
-  const __bf16 l = (__bf16)r;
-  *hi = __builtin_bit_cast(u16, h);
-  *lo = __builtin_bit_cast(u16, l);
-}
-
-__device__ __forceinline__ void store_lo(void* base, int prec, int64_t nn, int64_t idx, double v) {
-  if (prec == PREC_F32) {
-    ((float*)base)[idx] = (float)v;
-  } else {
-    u16 h, l;
-    split_bf16(v, &h, &l);
-    ((u16*)base)[idx] = h;
-    ((u16*)base)[nn + idx] = l;
-  }
+// The reduced-precision paths keep their intermediates in FP32; the split-BF16 pass splits its
+// A operand into BF16 (hi, lo) while staging it.
+__device__ __forceinline__ void store_lo(void* base, int64_t idx, double v) {
+  ((float*)base)[idx] = (float)v;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -169,7 +155,7 @@ __global__ __launch_bounds__(256) void k_rhs2d(const Lvl2D* __restrict__ levels,
     L.b64[c] = b;
   } else {
     L.b64[c] = b;
-    store_lo(L.lo0, L.prec, nn, c, b);
+    store_lo(L.lo0, c, b);
   }
 }
 
@@ -186,7 +172,7 @@ __global__ __launch_bounds__(256) void k_resid2d(const Lvl2D* __restrict__ level
   const int64_t c = (int64_t)iy * n + ix;
   const double x = L.x64[c];
   const double rho = L.b64[c] - (x - L.dt * L.nu_h2 * lap5(L.x64, iy, ix, n));
-  store_lo(L.lo0, L.prec, nn, c, rho);
+  store_lo(L.lo0, c, rho);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -238,9 +224,19 @@ __device__ __forceinline__ void fold_f32(u32x4 a, u32x4 m, u32x4* sum, u32x4* di
   *sum = __builtin_bit_cast(u32x4, flt4{x[0] + y[3], x[1] + y[2], x[2] + y[1], x[3] + y[0]});
   *dif = __builtin_bit_cast(u32x4, flt4{x[0] - y[3], x[1] - y[2], x[2] - y[1], x[3] - y[0]});
 }
-__device__ __forceinline__ float bf_to_f(unsigned short b) {
-  return __builtin_bit_cast(float, (unsigned int)b << 16);
+// 4 FP32 values -> BF16 hi (round to nearest) and BF16 lo (of the remainder), 8 bytes each
+__device__ __forceinline__ void split4_bf16(flt4 v, uint2* hi, uint2* lo) {
+  unsigned short h[4], l[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const __bf16 b = (__bf16)v[e];
+    h[e] = __builtin_bit_cast(unsigned short, b);
+    l[e] = __builtin_bit_cast(unsigned short, (__bf16)(v[e] - (float)b));
+  }
+  *hi = uint2{(unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16)};
+  *lo = uint2{(unsigned)l[0] | ((unsigned)l[1] << 16), (unsigned)l[2] | ((unsigned)l[3] << 16)};
 }
+
 // only the sums (sg = 1) or only the differences (sg = -1), for blocks whose output columns all
 // have one parity
 __device__ __forceinline__ u32x4 fold1_f64(u32x4 a, u32x4 m, double sg) {
@@ -253,45 +249,6 @@ __device__ __forceinline__ u32x4 fold1_f32(u32x4 a, u32x4 m, float sg) {
                                         x[3] + sg * y[0]});
 }
 
-// split BF16 operands (hi, lo): the folded values are formed in FP32 and split again
-__device__ __forceinline__ void fold_bf16(u32x4 ah, u32x4 al, u32x4 mh, u32x4 ml, u32x4* sh,
-                                          u32x4* sl, u32x4* dh, u32x4* dl) {
-  const u16x8 xh = __builtin_bit_cast(u16x8, ah), xl = __builtin_bit_cast(u16x8, al);
-  const u16x8 yh = __builtin_bit_cast(u16x8, mh), yl = __builtin_bit_cast(u16x8, ml);
-  u16x8 osh, osl, odh, odl;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const float x = bf_to_f(xh[e]) + bf_to_f(xl[e]);
-    const float y = bf_to_f(yh[7 - e]) + bf_to_f(yl[7 - e]);
-    const float su = x + y, di = x - y;
-    const __bf16 suh = (__bf16)su, dih = (__bf16)di;
-    osh[e] = __builtin_bit_cast(unsigned short, suh);
-    osl[e] = __builtin_bit_cast(unsigned short, (__bf16)(su - (float)suh));
-    odh[e] = __builtin_bit_cast(unsigned short, dih);
-    odl[e] = __builtin_bit_cast(unsigned short, (__bf16)(di - (float)dih));
-  }
-  *sh = __builtin_bit_cast(u32x4, osh);
-  *sl = __builtin_bit_cast(u32x4, osl);
-  *dh = __builtin_bit_cast(u32x4, odh);
-  *dl = __builtin_bit_cast(u32x4, odl);
-}
-__device__ __forceinline__ void fold1_bf16(u32x4 ah, u32x4 al, u32x4 mh, u32x4 ml, float sg,
-                                           u32x4* oh, u32x4* ol) {
-  const u16x8 xh = __builtin_bit_cast(u16x8, ah), xl = __builtin_bit_cast(u16x8, al);
-  const u16x8 yh = __builtin_bit_cast(u16x8, mh), yl = __builtin_bit_cast(u16x8, ml);
-  u16x8 h8, l8;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const float x = bf_to_f(xh[e]) + bf_to_f(xl[e]);
-    const float y = bf_to_f(yh[7 - e]) + bf_to_f(yl[7 - e]);
-    const float v = x + sg * y;
-    const __bf16 vh = (__bf16)v;
-    h8[e] = __builtin_bit_cast(unsigned short, vh);
-    l8[e] = __builtin_bit_cast(unsigned short, (__bf16)(v - (float)vh));
-  }
-  *oh = __builtin_bit_cast(u32x4, h8);
-  *ol = __builtin_bit_cast(u32x4, l8);
-}
 
 // FOLD (n a multiple of 64): the contraction runs over k < n/2 with the folded A operands and
 // E.Q the folded transform: row j' (n rows) holds Q_{k, perm(j')} for k < n/2, perm(j') = 2j'
@@ -349,7 +306,12 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   const int col0 = bx * BT;                  // columns of Q (j)
   if (row0 >= n || col0 >= n) return;
   const int64_t nn = (int64_t)n * n;
-  const T* A = (const T*)E.A;
+  // A arrives in FP64 or FP32 (the split-BF16 pass splits it while staging); Q in T
+  typedef typename std::conditional<PREC == PREC_BF16, float, T>::type TA;
+  constexpr int EA = 16 / (int)sizeof(TA);          // A elements per 16-byte chunk
+  constexpr int CHA = BK * (int)sizeof(TA) / 16;    // A chunks per row
+  constexpr int NAC = BT * CHA / NTHR;              // A chunks per thread
+  const TA* A = (const TA*)E.A;
   const T* Q = (const T*)E.Q;
   const int K = FOLD ? n / 2 : n;                   // contraction length
   const int64_t qsplit = (int64_t)n * K;            // BF16: lo part of the transform
@@ -370,27 +332,31 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   // global -> register staging of one k-slice (A, its mirrored columns when folding, Q); two
   // slices are in flight, so a slice's loads have two MFMA phases to arrive
   struct Slice {
-    u32x4 ra[NSPLIT][CPT], rm[NSPLIT][CPT], rb[NSPLIT][CPT];
+    u32x4 ra[NAC], rm[NAC], rb[NSPLIT][CPT];
   };
   Slice sl0, sl1;
   auto gload = [&](Slice& S, int k0) {
-    auto& ra = S.ra;
-    auto& rm = S.rm;
-    auto& rb = S.rb;
+#pragma unroll
+    for (int c = 0; c < NAC; ++c) {
+      const int id = tid + c * NTHR;
+      const int r = id / CHA, q = id % CHA;
+      const int ga = row0 + r;
+      const int64_t ko = k0 + q * EA;
+      const TA* arow = A + (int64_t)ga * n;
+      S.ra[c] = ga < n ? *(const u32x4*)(arow + ko) : u32x4{0, 0, 0, 0};
+      if constexpr (FOLD)
+        S.rm[c] = ga < n ? *(const u32x4*)(arow + (n - ko - EA)) : u32x4{0, 0, 0, 0};
+    }
 #pragma unroll
     for (int s = 0; s < NSPLIT; ++s)
 #pragma unroll
       for (int c = 0; c < CPT; ++c) {
         const int id = tid + c * NTHR;
         const int r = id / CH, q = id % CH;
-        const int ga = row0 + r, gb = col0 + r;         // Q symmetric: row j of Q = column j
+        const int gb = col0 + r;                        // Q symmetric: row j of Q = column j
         const int64_t ko = k0 + q * E16;
-        const T* arow = A + s * nn + (int64_t)ga * n;
-        ra[s][c] = ga < n ? *(const u32x4*)(arow + ko) : u32x4{0, 0, 0, 0};
-        if constexpr (FOLD)
-          rm[s][c] = ga < n ? *(const u32x4*)(arow + (n - ko - E16)) : u32x4{0, 0, 0, 0};
-        rb[s][c] = gb < n ? *(const u32x4*)(Q + s * qsplit + (int64_t)gb * K + ko)
-                          : u32x4{0, 0, 0, 0};
+        S.rb[s][c] = gb < n ? *(const u32x4*)(Q + s * qsplit + (int64_t)gb * K + ko)
+                            : u32x4{0, 0, 0, 0};
       }
   };
   // a block whose output columns all lie on one side of n/2 needs only the sums (side 0) or
@@ -418,48 +384,54 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
     }
   };
   auto sstore = [&](const Slice& S) {
-    const auto& ra = S.ra;
-    const auto& rm = S.rm;
-    const auto& rb = S.rb;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) {
+    for (int c = 0; c < NAC; ++c) {
       const int id = tid + c * NTHR;
-      const int r = id / CH, q = id % CH;
+      const int r = id / CHA, q = id % CHA;
       const int ro = r * LDE;                        // row start, in elements
-      if constexpr (!FOLD) {
-#pragma unroll
-        for (int s = 0; s < NSPLIT; ++s) put(As[0][s] + ro, q, ra[s][c]);
-      } else if constexpr (PREC == PREC_BF16) {
-        if (one_side) {
-          u32x4 oh, ol;
-          fold1_bf16(ra[0][c], ra[1][c], rm[0][c], rm[1][c], side ? -1.0f : 1.0f, &oh, &ol);
-          put(As[side][0] + ro, q, oh);
-          put(As[side][1] + ro, q, ol);
+      if constexpr (PREC == PREC_BF16) {
+        // 4 FP32 values (folded when FOLD) -> BF16 hi and lo at elements 4q .. 4q+3
+        auto put4 = [&](int a, u32x4 v) {
+          uint2 hi, lo;
+          split4_bf16(__builtin_bit_cast(flt4, v), &hi, &lo);
+          *(uint2*)(As[a][0] + ro + q * 4) = hi;
+          *(uint2*)(As[a][1] + ro + q * 4) = lo;
+        };
+        if constexpr (!FOLD) {
+          put4(0, S.ra[c]);
+        } else if (one_side) {
+          put4(side, fold1_f32(S.ra[c], S.rm[c], side ? -1.0f : 1.0f));
         } else {
-          u32x4 sh, sl, dh, dl;
-          fold_bf16(ra[0][c], ra[1][c], rm[0][c], rm[1][c], &sh, &sl, &dh, &dl);
-          put(As[0][0] + ro, q, sh);
-          put(As[0][1] + ro, q, sl);
-          put(As[1][0] + ro, q, dh);
-          put(As[1][1] + ro, q, dl);
+          u32x4 su, di;
+          fold_f32(S.ra[c], S.rm[c], &su, &di);
+          put4(0, su);
+          put4(1, di);
         }
+      } else if constexpr (!FOLD) {
+        put(As[0][0] + ro, q, S.ra[c]);
       } else if (one_side) {
         if constexpr (PREC == PREC_F64)
-          put(As[side][0] + ro, q, fold1_f64(ra[0][c], rm[0][c], side ? -1.0 : 1.0));
+          put(As[side][0] + ro, q, fold1_f64(S.ra[c], S.rm[c], side ? -1.0 : 1.0));
         else
-          put(As[side][0] + ro, q, fold1_f32(ra[0][c], rm[0][c], side ? -1.0f : 1.0f));
+          put(As[side][0] + ro, q, fold1_f32(S.ra[c], S.rm[c], side ? -1.0f : 1.0f));
       } else {
         u32x4 su, di;
         if constexpr (PREC == PREC_F64)
-          fold_f64(ra[0][c], rm[0][c], &su, &di);
+          fold_f64(S.ra[c], S.rm[c], &su, &di);
         else
-          fold_f32(ra[0][c], rm[0][c], &su, &di);
+          fold_f32(S.ra[c], S.rm[c], &su, &di);
         put(As[0][0] + ro, q, su);
         put(As[1][0] + ro, q, di);
       }
-#pragma unroll
-      for (int s = 0; s < NSPLIT; ++s) put(Bs[s] + ro, q, rb[s][c]);
     }
+#pragma unroll
+    for (int s = 0; s < NSPLIT; ++s)
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int id = tid + c * NTHR;
+        const int r = id / CH, q = id % CH;
+        put(Bs[s] + r * LDE, q, S.rb[s][c]);
+      }
   };
 
   // the A operand of each 16-column group of this wave: sums (0) for even output columns,
@@ -657,18 +629,6 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       for (int e = 0; e < ET; e += 4)
         *(flt4*)((float*)E.C + o + e) =
             flt4{(float)v[e], (float)v[e + 1], (float)v[e + 2], (float)v[e + 3]};
-    } else if constexpr (OUT == OUT_BF16) {
-      static_assert(ET == 8, "BF16 runs are 16 bytes");
-      u16x8 hv, lv;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        u16 h, l;
-        split_bf16(v[e], &h, &l);
-        hv[e] = h;
-        lv[e] = l;
-      }
-      *(u16x8*)((u16*)E.C + o) = hv;
-      *(u16x8*)((u16*)E.C + nn + o) = lv;
     } else {
 #pragma unroll
       for (int e = 0; e < ET; e += 2) {
@@ -805,7 +765,7 @@ hipError_t allow_wide_out() {
 // the outputs each precision's passes use: its own type, the FP64 first solve, the final update
 template <int PREC>
 hipError_t allow_wide() {
-  constexpr int OWN = PREC == PREC_F64 ? OUT_F64 : (PREC == PREC_F32 ? OUT_F32 : OUT_BF16);
+  constexpr int OWN = PREC == PREC_F64 ? OUT_F64 : OUT_F32;
   hipError_t e = allow_wide_out<PREC, OWN>();
   if (e == hipSuccess && OWN != OUT_F64) e = allow_wide_out<PREC, OUT_F64>();
   if (e == hipSuccess) e = allow_wide_out<PREC, OUT_FINAL>();
@@ -977,14 +937,14 @@ void run_stages(int prec, const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nma
     launch_pass<PREC_F32, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_F32, OUT_FINAL>(d + 7 * cnt, lv, cnt, nmax, s, st);
   } else {
-    launch_pass<PREC_BF16, OUT_BF16>(d + 0 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_BF16>(d + 1 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_BF16>(d + 2 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 0 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_BF16, OUT_F64>(d + 3 * cnt, lv, cnt, nmax, s, st);
     hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, cnt), dim3(256), 0, st, lv, s);
-    launch_pass<PREC_BF16, OUT_BF16>(d + 4 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_BF16>(d + 5 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_BF16>(d + 6 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_BF16, OUT_FINAL>(d + 7 * cnt, lv, cnt, nmax, s, st);
   }
 }
@@ -1130,7 +1090,7 @@ int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, do
     else if (pl->prec == PREC_F32)
       launch_pass<PREC_F32, OUT_F32>(pl->d_passes, pl->d_levels, P, n, sigma, stream);
     else
-      launch_pass<PREC_BF16, OUT_BF16>(pl->d_passes, pl->d_levels, P, n, sigma, stream);
+      launch_pass<PREC_BF16, OUT_F32>(pl->d_passes, pl->d_levels, P, n, sigma, stream);
   };
   one();
   (void)hipEventRecord(a, stream);
