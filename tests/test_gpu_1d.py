@@ -311,3 +311,47 @@ def test_fused_integration_equals_per_step_kernel(env, bc, n, order, nt):
     p = Problem(dim=1, bc=bc, n=n, length=length, fe=prob["fe"], a=0.6, nu=2e-3, dt=0.05 / nt)
     ref = ridc_pipelined(p, u0, nt, order)[-1]
     assert rel_l2(fused, ref) <= TOL
+
+
+def test_batch_kernel_time_and_its_errors(env):
+    torch, ridc = env
+    cases = workloads.config_batched_1d(count=6, nt=40, T=0.01)
+    solvers = [ridc.Ridc(p) for p, _ in cases]
+    x0s = [torch.tensor(u, dtype=torch.float64, device="cuda") for _, u in cases]
+    try:
+        with pytest.raises(ridc.RidcError) as ei:          # not armed
+            ridc.batch_kernel_time(solvers, 5)
+        assert ei.value.code == ridc.RIDC_E_STATE
+        for s, x0, (p, _) in zip(solvers, x0s, cases):
+            s.begin(x0, p["nt"])
+        with pytest.raises(ridc.RidcError) as ei:          # start-up step: not every level active
+            ridc.batch_kernel_time(solvers, 5)
+        assert ei.value.code == ridc.RIDC_E_STATE
+        ridc.advance(solvers, 6)
+        us, nbytes = ridc.batch_kernel_time(solvers, 10)
+        assert us > 0
+        assert nbytes == sum(s.step_cost()[0] for s in solvers)
+        # the handles did not advance: the integration finishes with the solo bits
+        while any(s.remaining() > 0 for s in solvers):
+            ridc.advance(solvers, 64)
+        for s, x0, (p, _) in zip(solvers, x0s, cases):
+            out = torch.empty_like(x0)
+            s.read(out)
+            s.sync()
+            solo = ridc.Ridc(p)
+            np.testing.assert_array_equal(out.cpu().numpy(), solo.integrate(x0, p["nt"]).cpu().numpy())
+            solo.close()
+    finally:
+        for s in solvers:
+            s.close()
+
+
+def test_stencil_time_is_2d_only(env):
+    torch, ridc = env
+    prob, u0 = workloads.config_advdiff_1d(n=64, nt=20)
+    s = ridc.Ridc(prob)
+    s.begin(torch.tensor(u0, dtype=torch.float64, device="cuda"), 20)
+    with pytest.raises(ridc.RidcError) as ei:
+        s.stencil_time(5)
+    assert ei.value.code == ridc.RIDC_E_UNSUPPORTED
+    s.close()

@@ -135,3 +135,24 @@ def test_full_size_against_reference_samples(env, prec):
     err = rel_l2(sub, ref["top_sub8"])
     _say(f"  top level on the 128^2 sub-grid: rel L2 {err:.3e}")
     assert err <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_stencil_time_bytes(env, prec):
+    """The right-hand-side kernel's algorithmic bytes: every level reads its value and (j > 0)
+    its j+1 window vectors, and writes the FP64 right-hand side plus a 4-byte copy in the
+    reduced-precision paths."""
+    torch, ridc = env
+    n, P = 128, 4
+    prob, u0 = workloads.config_reacdiff_2d(n=n, nt=12, order=P, T=0.02)
+    s = ridc.Ridc(prob, prec=prec)
+    s.begin(torch.tensor(u0.reshape(-1), dtype=torch.float64, device="cuda"), 12)
+    with pytest.raises(ridc.RidcError):                    # start-up step
+        s.stencil_time(3)
+    ridc.advance([s], P * (P - 1) // 2)
+    us, nbytes = s.stencil_time(5)
+    lo = 0 if prec == "fp64" else 4
+    want = sum(8 * (1 if j == 0 else j + 2) + 8 + lo for j in range(P)) * n * n
+    assert us > 0 and nbytes == want
+    s.sync()
+    s.close()
