@@ -41,12 +41,12 @@ KERNEL_SOURCE = {
 MEASURED_TRAFFIC = {
     ("reacdiff1d", (1024, 128, 1)): ("1d", "cac06158088743f9", 4503552),
     ("batched1d", (512, 1536)): ("1d", "cac06158088743f9", 74536141),
-    ("reacdiff2d_rhs", "fp64"): ("2d", "517a71ed6d09edea", 174545920),
-    ("reacdiff2d", "fp64"): ("2d", "517a71ed6d09edea", 100908237),
-    ("reacdiff2d_rhs", "fp32"): ("2d", "517a71ed6d09edea", 193864090),
-    ("reacdiff2d", "fp32"): ("2d", "517a71ed6d09edea", 50575155),
-    ("reacdiff2d_rhs", "bf16x3"): ("2d", "517a71ed6d09edea", 193878835),
-    ("reacdiff2d", "bf16x3"): ("2d", "517a71ed6d09edea", 50569011),
+    ("reacdiff2d_rhs", "fp64"): ("2d", "2c0568b454154fcf", 174545920),
+    ("reacdiff2d", "fp64"): ("2d", "2c0568b454154fcf", 100908237),
+    ("reacdiff2d_rhs", "fp32"): ("2d", "2c0568b454154fcf", 193864090),
+    ("reacdiff2d", "fp32"): ("2d", "2c0568b454154fcf", 50575155),
+    ("reacdiff2d_rhs", "bf16x3"): ("2d", "2c0568b454154fcf", 193878835),
+    ("reacdiff2d", "bf16x3"): ("2d", "2c0568b454154fcf", 50569011),
 }
 
 

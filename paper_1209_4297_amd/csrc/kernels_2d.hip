@@ -18,7 +18,9 @@
 // A pass is a GEMM on the matrix cores (v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32, or three
 // v_mfma_f32_16x16x32_bf16 products of hi/lo BF16 splits), batched over every active level of
 // every instance in one launch; the eigenvalue divide and the final update are fused into the
-// epilogues of passes 2 and 4.
+// epilogues of passes 2 and 4.  Sides that are multiples of 64 fold Q by its reflection
+// symmetry, Q_{n-1-k, j} = (-1)^j Q_{k, j}, which halves the contraction (k_pass2d).  The
+// split-BF16 path keeps its intermediates in FP32 and splits its operand while staging it.
 //
 // Reduced precision (FP32 or split BF16) adds one FP64 residual refinement:
 //   x1 = S~(b),  rho = b - (x1 - dt nu Lap_h x1)  (FP64 5-point),  x = x1 + S~(rho).
