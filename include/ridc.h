@@ -177,7 +177,8 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32
  * workgroup, else chunks of `rows` rows (allowed when the PCR coupling vanishes within a halo
  * shorter than the system); flags bit 0 = write level values with nontemporal stores; flags
  * bit 1 = one workgroup of `threads` (512 or 1024, rows 0) runs every level and many pipeline
- * steps in one launch (needs the levels' cycles to fit one CU's LDS, order <= 6).
+ * steps in one launch (needs the levels' cycles to fit one CU's LDS; order <= 6 with 512
+ * threads, order <= 4 with 1024).
  * Errors: RIDC_E_INVAL if the tiling does not fit.                                            */
 int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags);
 

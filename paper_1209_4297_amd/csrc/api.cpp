@@ -188,6 +188,7 @@ struct FusedPlan {
 FusedPlan plan_fused(const ridc_problem* p, int threads) {
   FusedPlan f;
   if (p->dim != 1 || p->order > kMaxJ1024 + 1) return f;
+  if (threads == 1024 && p->order > 4) return f;   // the 1024-thread kernel covers orders <= 4
   const int P = p->order;
   const int64_t ms = p->bc == RIDC_BC_PERIODIC ? p->n : p->n + 2;
   const size_t maxl = (size_t)device_max_lds();

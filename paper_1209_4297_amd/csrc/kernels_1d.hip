@@ -652,9 +652,8 @@ hipError_t launch_fused_1d(const Fused1D* d_items, const Fused1D* one, int count
     if (max_order <= kMaxJ1024 + 1)
       return fused_launch<kMaxJ1024, 512>(d_items, one, count, lds_bytes, stream);
   } else if (threads == 1024) {
+    // orders 5 and 6 would spill at 1024 threads (128 registers): they take 512
     if (max_order <= 4) return fused_launch<3, 1024>(d_items, one, count, lds_bytes, stream);
-    if (max_order <= kMaxJ1024 + 1)
-      return fused_launch<kMaxJ1024, 1024>(d_items, one, count, lds_bytes, stream);
   }
   return hipErrorInvalidValue;
 }

@@ -133,7 +133,7 @@ hipError_t launch_1d_solo(const Solo1D& a, int nblocks, int threads, int max_ord
 // each, two LDS buffers of n (periodic) or n+2 (Dirichlet) doubles per level, level groups of
 // Fused1D::group = (threads / P) rounded down to whole waves).  `one` (nullable): a single instance whose descriptor goes in the
 // kernel arguments; otherwise d_items holds `count` device descriptors.  max_order: the
-// largest order among the instances (at most kMaxJ1024 + 1).
+// largest order among the instances (at most kMaxJ1024 + 1; at most 4 with 1024 threads).
 hipError_t launch_fused_1d(const Fused1D* d_items, const Fused1D* one, int count, int max_order,
                            int threads, size_t lds_bytes, hipStream_t stream);
 
