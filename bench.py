@@ -39,8 +39,8 @@ KERNEL_SOURCE = {
     "2d": os.path.join(ROOT, "paper_1209_4297_amd", "csrc", "kernels_2d.hip"),
 }
 MEASURED_TRAFFIC = {
-    ("reacdiff1d", (1024, 128, 1)): ("1d", "cac06158088743f9", 4503552),
-    ("batched1d", (512, 1536)): ("1d", "cac06158088743f9", 74536141),
+    ("reacdiff1d", (1024, 128, 1)): ("1d", "a1984401034a7e56", 4536320),
+    ("batched1d", (512, 1536)): ("1d", "a1984401034a7e56", 74555392),
     ("reacdiff2d_rhs", "fp64"): ("2d", "2c0568b454154fcf", 174545920),
     ("reacdiff2d", "fp64"): ("2d", "2c0568b454154fcf", 100908237),
     ("reacdiff2d_rhs", "fp32"): ("2d", "2c0568b454154fcf", 193864090),
