@@ -602,10 +602,17 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
         const int jl0 = wn + 16 * b;
         if (jl0 < jr || jl0 >= jr + RJ) continue;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a) {
+          ST* dst = stg + (jl0 - jr + j_l) * SS + wm + 16 * a + i_base;
+          if constexpr (PREC == PREC_F64) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            stg[(jl0 - jr + j_l) * SS + wm + 16 * a + i_base + i_step * r] = (ST)acc[a][b][r];
+            for (int r = 0; r < 4; ++r) dst[i_step * r] = acc[a][b][r];
+          } else {
+            // FP32 tiles hold 4 consecutive rows per lane: one 16-byte store (16-byte aligned:
+            // SS, wm, 16a and i_base are multiples of 4)
+            *(flt4*)dst = acc[a][b];
+          }
+        }
       }
     }
     __syncthreads();
@@ -616,8 +623,21 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
     const int j = FOLD ? (jp < half ? 2 * jp : 2 * (jp - half) + 1) : jp;
     const int64_t o = (int64_t)j * n + i0;
     double v[ET];
+    if constexpr (PREC == PREC_F64) {
 #pragma unroll
-    for (int e = 0; e < ET; ++e) v[e] = (double)stg[orow * SS + oc + e];
+      for (int e = 0; e < ET; e += 2) {
+        const dbl2 w = *(const dbl2*)(stg + orow * SS + oc + e);
+        v[e] = w[0];
+        v[e + 1] = w[1];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < ET; e += 4) {
+        const flt4 w = *(const flt4*)(stg + orow * SS + oc + e);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[e + t] = (double)w[t];
+      }
+    }
     if (E.divide) {
       const double lj = E.lam[j];
 #pragma unroll
