@@ -311,7 +311,7 @@ void build_items_1d(ridc_handle* h, const Tile1D& tile) {
     it.dt = p.dt;
     it.ce = explicit_coeff(p.fe_kind, p.a, h->h);
     it.nu_h2 = p.nu / (h->h * h->h);
-    it.divisor = h->pcr.divisor;
+    it.inv_divisor = 1.0 / h->pcr.divisor;
     for (int k = 0; k < h->pcr.stages; ++k) {
       it.gamma[k] = h->pcr.gamma[k];
       it.shift[k] = (int32_t)h->pcr.shift[k];
@@ -348,7 +348,7 @@ void build_items_1d(ridc_handle* h, const Tile1D& tile) {
   a.dt = p.dt;
   a.ce = explicit_coeff(p.fe_kind, p.a, h->h);
   a.nu_h2 = p.nu / (h->h * h->h);
-  a.divisor = h->pcr.divisor;
+  a.inv_divisor = 1.0 / h->pcr.divisor;
   h->solo_blocks = P * nchunks;
 }
 
@@ -829,7 +829,7 @@ int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out) {
       F.dt = p->dt;
       F.ce = h->solo.ce;
       F.nu_h2 = h->solo.nu_h2;
-      F.divisor = h->pcr.divisor;
+      F.inv_divisor = 1.0 / h->pcr.divisor;
     }
     if (hipMemcpy(h->d_blocks, h->blocks.data(), sizeof(Blk1D) * h->blocks.size(),
                   hipMemcpyHostToDevice) != hipSuccess ||

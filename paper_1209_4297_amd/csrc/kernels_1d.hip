@@ -16,7 +16,8 @@
 // (zero ghosts) are solved as the odd extension to a cyclic system of m = 2n+2 rows (row 0 and
 // row n+1 are the ghosts, rows n+2.. mirror rows n..1 with a sign flip), which reproduces the
 // Dirichlet solution exactly.  Each PCR stage k updates every row with the same coefficient:
-// d_i <- d_i - gamma_k (d_{i-s} + d_{i+s}), s = 2^k mod m; after the last stage x = d / divisor.
+// d_i <- d_i - gamma_k (d_{i-s} + d_{i+s}), s = 2^k mod m; after the last stage x = d / divisor,
+// taken as a product with the divisor's reciprocal.
 // In "wrap" mode one workgroup holds the whole cycle and indexes it modulo m.  In "chunk" mode
 // (used when the coupling falls below rounding after K stages) a workgroup computes B rows
 // and carries a halo of 2^K - 1 rows on each side, recomputing the halo's right-hand side; the
@@ -90,9 +91,9 @@ __device__ __forceinline__ double from_lane_above(double v) {
 // value the zero-ghost stencil needs beyond either end.  Every row computes
 //   u + dt f_E(u) + sum_i [cf_i f_E(v_i) + cl_i L v_i]
 // at its grid row with the same operations in every tiling.  The pass loop is uniform per wave.
-template <int J>
-__device__ __forceinline__ void rhs_rows(const Geo& G, const Step<J>& S, int gbase, int count,
-                                         double* __restrict__ d, int wave, int nw, int lane) {
+template <int J, bool PER>
+__device__ __forceinline__ void rhs_rows_bc(const Geo& G, const Step<J>& S, int gbase, int count,
+                                            double* __restrict__ d, int wave, int nw, int lane) {
   const int n = G.n, M = G.M;
   for (int base = wave * 62; base < count; base += nw * 62) {
     const int l = base + lane - 1;
@@ -103,7 +104,7 @@ __device__ __forceinline__ void rhs_rows(const Geo& G, const Step<J>& S, int gba
     else if (g >= M) g -= M;
     bool ghost = false, mir = false;
     int p = g;
-    if (!G.per) {
+    if constexpr (!PER) {
       ghost = g == 0 || g == n + 1;
       mir = g > n + 1;
       p = ghost ? 0 : (mir ? M - g - 1 : g - 1);
@@ -139,6 +140,16 @@ __device__ __forceinline__ void rhs_rows(const Geo& G, const Step<J>& S, int gba
   }
 }
 
+// periodic cycles have no ghost or mirror rows: their gather is compiled without them
+template <int J>
+__device__ __forceinline__ void rhs_rows(const Geo& G, const Step<J>& S, int gbase, int count,
+                                         double* __restrict__ d, int wave, int nw, int lane) {
+  if (G.per)
+    rhs_rows_bc<J, true>(G, S, gbase, count, d, wave, nw, lane);
+  else
+    rhs_rows_bc<J, false>(G, S, gbase, count, d, wave, nw, lane);
+}
+
 // Everything one level step reads besides the rings: built from a descriptor table entry
 // (batched launches) or from the kernel arguments (a single instance's launch).
 struct View {
@@ -148,7 +159,7 @@ struct View {
   const double* gamma;
   const int* shift;
   int R_own, R_prev, n, M, bc, fe, stages, wrap, B, H;
-  double dt, ce, nu_h2, divisor;
+  double dt, ce, nu_h2, inv_divisor;
 };
 
 __device__ __forceinline__ void store_row(double* p, double v, bool nt) {
@@ -198,7 +209,7 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
   const int n = G.n, M = G.M;
   const bool per = G.per;
   const int stages = L.stages;
-  const double divisor = L.divisor;
+  const double inv_div = L.inv_divisor;
   const double* __restrict__ gam = L.gamma;
 
   if (L.wrap) {
@@ -234,7 +245,7 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
       d1 = t;
     }
     for (int l = l0 + threadIdx.x; l < l1; l += T)
-      store_row(S.out + (per ? l : l - 1), d0[l] / divisor, nt_store);
+      store_row(S.out + (per ? l : l - 1), d0[l] * inv_div, nt_store);
     return;
   }
 
@@ -281,7 +292,7 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
   const int last = per ? n : n + 1;                   // one past the last physical row of g
   for (int l = H + threadIdx.x; l < H + B; l += T) {
     const int g = g0 - H + l;
-    if (g < last) store_row(S.out + (per ? g : g - 1), d0[l] / divisor, nt_store);
+    if (g < last) store_row(S.out + (per ? g : g - 1), d0[l] * inv_div, nt_store);
   }
 }
 
@@ -319,7 +330,7 @@ __global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
   const int64_t m = sigma - L->sigma0 - (int64_t)j * (j + 1) / 2;  // time index computed now
   if (m < 1 || m > L->nt) return;                                   // level idle this step
   View v{L->own, L->prev, L->W, L->gamma, L->shift, L->R_own, L->R_prev, L->n, L->M, L->bc,
-         L->fe, L->stages, L->wrap, L->B, L->H, L->dt, L->ce, L->nu_h2, L->divisor};
+         L->fe, L->stages, L->wrap, L->B, L->H, L->dt, L->ce, L->nu_h2, L->inv_divisor};
   dispatch_level<T, MJ>(j, v, bk.chunk, m, lds, false);
 }
 
@@ -334,7 +345,7 @@ __global__ __launch_bounds__(T) void k_step1d_solo(const Solo1D a, int64_t sigma
   if (m < 1 || m > a.nt) return;
   View v{a.ring[j], j > 0 ? a.ring[j - 1] : nullptr, a.W[j], a.gamma, a.shift, a.R[j],
          j > 0 ? a.R[j - 1] : 1, a.n, a.M, a.bc, a.fe, a.stages, a.wrap, a.B, a.H, a.dt,
-         a.ce, a.nu_h2, a.divisor};
+         a.ce, a.nu_h2, a.inv_divisor};
   dispatch_level<T, MJ>(j, v, chunk, m, lds, a.nt_store != 0);
 }
 
@@ -392,7 +403,7 @@ __device__ __forceinline__ void fused_body(const Fused1D& F) {
   if (mine) {
     v = View{F.ring[j], j > 0 ? F.ring[j - 1] : nullptr, F.W[j], F.gamma, F.shift, F.R[j],
              j > 0 ? F.R[j - 1] : 1, n, M, F.bc, F.fe, F.stages, 1, 0, 0, F.dt, F.ce, F.nu_h2,
-             F.divisor};
+             F.inv_divisor};
     // Dirichlet ghost rows (0 and n+1) must read zero in both buffers whatever their roles: a
     // level waiting for its start-up swaps the buffers without writing them
     for (int l = lt; l < ms; l += G) {
@@ -447,7 +458,7 @@ __device__ __forceinline__ void fused_body(const Fused1D& F) {
     }
     if (act) {
       double* out = F.ring[j] + (m % F.R[j]) * (int64_t)n;
-      for (int l = l0 + lt; l < l1; l += G) out[per ? l : l - 1] = d0[l] / F.divisor;
+      for (int l = l0 + lt; l < l1; l += G) out[per ? l : l - 1] = d0[l] * F.inv_divisor;
     }
     __syncthreads();                         // this step's values before the next step reads
   }

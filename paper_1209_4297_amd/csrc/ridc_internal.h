@@ -80,7 +80,7 @@ struct Lvl1D {
   double dt;
   double ce;               // coefficient of the explicit stencil (see explicit_coeff)
   double nu_h2;            // nu / h^2
-  double divisor;          // final PCR divisor
+  double inv_divisor;      // 1 / final PCR divisor
   double gamma[kMaxPcr];
   int32_t shift[kMaxPcr];  // 2^k mod M
 };
@@ -94,7 +94,7 @@ struct Solo1D {
   int32_t R[kMaxOrder];        // ring slots per level
   int64_t nt;
   int32_t nchunks, n, M, bc, fe, stages, wrap, B, H, nt_store;
-  double dt, ce, nu_h2, divisor;
+  double dt, ce, nu_h2, inv_divisor;
 };
 
 // One instance integrated by the fused kernel (one workgroup): pipeline steps
@@ -108,7 +108,7 @@ struct Fused1D {
   int32_t R[kMaxOrder];
   int64_t nt, sigma0, sigma_first, sigma_last;
   int32_t P, group, n, M, bc, fe, stages, pad;
-  double dt, ce, nu_h2, divisor;
+  double dt, ce, nu_h2, inv_divisor;
 };
 
 struct Blk1D {
