@@ -198,13 +198,39 @@ def test_batch_tilings_are_bitwise_identical(env, policy):
 
 
 def test_graph_and_direct_launch_agree(env, monkeypatch):
+    """On a stream of its own an integration is captured in a HIP graph and replayed (a second
+    call replays the cached graph); it must give the bits of direct launches, on that stream
+    with capture switched off and on the null stream."""
+    torch, _ = env
     prob, u0 = workloads.config_reacdiff_1d(n=2048, nt=300, T=0.15)
-    a, _ = run_gpu(env, prob, u0, levels=False)
-    b, _ = run_gpu(env, prob, u0, levels=False)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a, _ = run_gpu(env, prob, u0, levels=False)          # captured
+        b, _ = run_gpu(env, prob, u0, levels=False)
+    direct, _ = run_gpu(env, prob, u0, levels=False)          # null stream: direct launches
     monkeypatch.setenv("RIDC_GRAPH", "0")
-    c, _ = run_gpu(env, prob, u0, levels=False)
+    with torch.cuda.stream(side):
+        c, _ = run_gpu(env, prob, u0, levels=False)
     np.testing.assert_array_equal(a, b)
     np.testing.assert_array_equal(a, c)
+    np.testing.assert_array_equal(a, direct)
+
+
+def test_graph_replay_of_one_handle(env):
+    """One handle integrating twice on its own stream replays its cached graph."""
+    torch, ridc = env
+    prob, u0 = workloads.config_advdiff_1d(n=256, nt=60)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        s = ridc.Ridc(prob)
+        x0 = torch.tensor(u0, dtype=torch.float64, device="cuda")
+        first = s.integrate(x0, 60).clone()
+        second = s.integrate(x0, 60)
+        side.synchronize()
+        s.close()
+    alone, _ = run_gpu(env, prob, u0, levels=False)
+    np.testing.assert_array_equal(first.cpu().numpy(), alone)
+    np.testing.assert_array_equal(second.cpu().numpy(), alone)
 
 
 def test_nonfinite_is_reported(env):

@@ -156,3 +156,42 @@ def test_stencil_time_bytes(env, prec):
     assert us > 0 and nbytes == want
     s.sync()
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_graph_and_direct_launch_agree_2d(env, prec, monkeypatch):
+    torch, _ = env
+    prob, u0 = workloads.config_reacdiff_2d(n=128, nt=20, order=4, T=0.04, nu=1e-3)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a, _ = run2d(env, prob, u0, prec, levels=False)       # captured and replayed
+    direct, _ = run2d(env, prob, u0, prec, levels=False)      # null stream
+    monkeypatch.setenv("RIDC_GRAPH", "0")
+    with torch.cuda.stream(side):
+        c, _ = run2d(env, prob, u0, prec, levels=False)
+    np.testing.assert_array_equal(a, direct)
+    np.testing.assert_array_equal(a, c)
+
+
+def test_batch_mixing_1d_and_2d(env):
+    """One batched integration over 1D and 2D instances (and two precisions) gives every
+    instance the bits of its solo integration."""
+    torch, ridc = env
+    cases = [(workloads.config_reacdiff_2d(n=128, nt=16, order=3, T=0.03, nu=1e-3), "fp64"),
+             (workloads.config_reacdiff_2d(n=96, nt=12, order=4, T=0.02, nu=1e-3), "fp32"),
+             (workloads.config_reacdiff_1d(n=700, nt=30, order=4, T=0.02), "fp64"),
+             (workloads.config_advdiff_1d(n=300, nt=25, order=2), "fp64")]
+    solvers, u0s, uTs, solo = [], [], [], []
+    for (prob, u0), prec in cases:
+        s = ridc.Ridc(prob, prec=prec)
+        x0 = torch.tensor(np.asarray(u0).reshape(-1), dtype=torch.float64, device="cuda")
+        solo.append(s.integrate(x0, prob["nt"]).cpu().numpy())
+        solvers.append(s)
+        u0s.append(x0)
+        uTs.append(torch.empty_like(x0))
+    ridc.integrate_batch(solvers, u0s, [p["nt"] for (p, _), _ in cases], uTs)
+    torch.cuda.synchronize()
+    for s, uT, ref in zip(solvers, uTs, solo):
+        s.sync()
+        np.testing.assert_array_equal(uT.cpu().numpy(), ref)
+        s.close()
