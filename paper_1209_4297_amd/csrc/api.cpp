@@ -64,7 +64,6 @@ struct ridc_handle {
   int solo_blocks = 0;
   // fused integration (one workgroup per instance) when the levels fit one CU's LDS
   bool fused = false;          // whole-range workgroup in use
-  bool fused_ok = false;       // the levels fit one CU's LDS
   int fused_threads = 512;
   size_t fused_lds = 0;
   Fused1D fused_item{};
@@ -804,7 +803,6 @@ int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out) {
     cur += L.blocks;
     h->blocks_cap = (size_t)L.nblocks;
     build_items_1d(h, tile);
-    h->fused_ok = plan_fused(p, 512).ok;
     h->fused = tile.fused != 0;
     h->fused_threads = tile.fused ? tile.fused : 512;
     const FusedPlan fp = plan_fused(p, h->fused_threads);
@@ -1108,8 +1106,6 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32
     if (flags_out) *flags_out = 0;
     return RIDC_OK;                      // 2D launch shapes are fixed per precision
   }
-  const size_t ring_bytes = 0;
-  (void)ring_bytes;
   // the tuning steps overwrite the rings: start from zeros, leave the handle unarmed
   int64_t slots = 0;
   for (int j = 0; j < h->P; ++j) slots += h->R[j];
