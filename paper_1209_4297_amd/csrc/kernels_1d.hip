@@ -44,10 +44,6 @@ __device__ __forceinline__ double fe_eval(int fe, double ce, double um, double u
   return 0.0;
 }
 
-__device__ __forceinline__ bool fe_stencil(int fe) {
-  return fe == RIDC_FE_ADVECT_C2 || fe == RIDC_FE_ADVECT_UPWIND || fe == RIDC_FE_BURGERS;
-}
-
 // Per-workgroup view of one level step of level J: where the level's value and the previous
 // level's window live this step, and the coefficients that fold eq. (corr) into one sum over the
 // window:

@@ -170,7 +170,6 @@ __global__ __launch_bounds__(256) void k_resid2d(const Lvl2D* __restrict__ level
   const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
   const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (ix >= n || iy >= n) return;
-  const int64_t nn = (int64_t)n * n;
   const int64_t c = (int64_t)iy * n + ix;
   const double x = L.x64[c];
   const double rho = L.b64[c] - (x - L.dt * L.nu_h2 * lap5(L.x64, iy, ix, n));
