@@ -23,7 +23,9 @@
 // split-BF16 path keeps its intermediates in FP32 and splits its operand while staging it.
 //
 // Reduced precision (FP32 or split BF16) adds one FP64 residual refinement:
-//   x1 = S~(b),  rho = b - (x1 - dt nu Lap_h x1)  (FP64 5-point),  x = x1 + S~(rho).
+//   x1 = S~(b),  rho = b - (x1 - dt nu Lap_h x1)  (FP64 5-point),  x = x1 + S~(rho);
+// x1 is held in FP32: the pass that produces it accumulates in FP32 (no divide), so x1 is an
+// FP32 value and storing it in FP32 loses nothing.
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
@@ -63,7 +65,7 @@ struct Lvl2D {
 struct Pass2D {
   const void* A;        // input, row-major n x n (FP64, or FP32 in the reduced-precision paths)
   void* C;              // output (unless final)
-  const double* add;    // final epilogue: extra FP64 term (x1 of the refinement), nullable
+  const float* add;     // final epilogue: extra term (x1 of the refinement, FP32), nullable
   const void* Q;        // transform matrix in the input precision (BF16: hi, lo at +n*n)
   const double* lam;    // dt nu mu_k (divide epilogue)
   int32_t level;        // index into the level table
@@ -102,13 +104,14 @@ __device__ __forceinline__ double fe2(int fe, double u) {
   return fe == RIDC_FE_LOGISTIC ? u * (1.0 - u) : 0.0;
 }
 
-__device__ __forceinline__ double lap5(const double* __restrict__ v, int iy, int ix, int n) {
+template <typename V>
+__device__ __forceinline__ double lap5(const V* __restrict__ v, int iy, int ix, int n) {
   const int64_t c = (int64_t)iy * n + ix;
-  const double w = ix > 0 ? v[c - 1] : 0.0;
-  const double e = ix < n - 1 ? v[c + 1] : 0.0;
-  const double s = iy > 0 ? v[c - n] : 0.0;
-  const double no = iy < n - 1 ? v[c + n] : 0.0;
-  return ((w + e) + (s + no)) - 4.0 * v[c];
+  const double w = ix > 0 ? (double)v[c - 1] : 0.0;
+  const double e = ix < n - 1 ? (double)v[c + 1] : 0.0;
+  const double s = iy > 0 ? (double)v[c - n] : 0.0;
+  const double no = iy < n - 1 ? (double)v[c + n] : 0.0;
+  return ((w + e) + (s + no)) - 4.0 * (double)v[c];
 }
 
 // The reduced-precision paths keep their intermediates in FP32; the split-BF16 pass splits its
@@ -171,8 +174,11 @@ __global__ __launch_bounds__(256) void k_resid2d(const Lvl2D* __restrict__ level
   const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (ix >= n || iy >= n) return;
   const int64_t c = (int64_t)iy * n + ix;
-  const double x = L.x64[c];
-  const double rho = L.b64[c] - (x - L.dt * L.nu_h2 * lap5(L.x64, iy, ix, n));
+  // the first solve x1 is held in FP32 (in the x64 buffer; it leaves an FP32 accumulator, so
+  // nothing is lost), the residual is formed in FP64
+  const float* x1 = (const float*)L.x64;
+  const double x = x1[c];
+  const double rho = L.b64[c] - (x - L.dt * L.nu_h2 * lap5(x1, iy, ix, n));
   store_lo(L.lo0, c, rho);
 }
 
@@ -576,7 +582,9 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   const int orow = tid / (BT / ET);                   // this thread's output row in a round
   const int oc = (tid % (BT / ET)) * ET;              // and its first element
   // the final update's FP64 operands (base, add) of this thread's run, loaded one round ahead
-  dbl2 bq[2][ET / 2], aq[2][ET / 2];
+  dbl2 bq[2][ET / 2];
+  typedef float flt2 __attribute__((ext_vector_type(2)));
+  flt2 aq[2][ET / 2];
   auto fetch = [&](int jr, int slot) {
     if constexpr (OUT == OUT_FINAL) {
       const int jp = col0 + jr + orow;
@@ -587,7 +595,7 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
 #pragma unroll
       for (int e = 0; e < ET / 2; ++e) {
         bq[slot][e] = *(const dbl2*)(base + o + 2 * e);
-        aq[slot][e] = E.add ? *(const dbl2*)(E.add + o + 2 * e) : dbl2{0.0, 0.0};
+        aq[slot][e] = E.add ? *(const flt2*)(E.add + o + 2 * e) : flt2{0.0f, 0.0f};
       }
     }
   };
@@ -654,7 +662,7 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
 #pragma unroll
       for (int e = 0; e < ET; e += 2) {
         const dbl2 bs = bq[cur][e / 2];
-        const dbl2 ad = aq[cur][e / 2];
+        const dbl2 ad = dbl2{(double)aq[cur][e / 2][0], (double)aq[cur][e / 2][1]};
         *(dbl2*)(out64 + o + e) = dbl2{bs[0] + (ad[0] + v[e]), bs[1] + (ad[1] + v[e + 1])};
       }
     }
@@ -783,12 +791,11 @@ hipError_t allow_wide_out() {
                              (int)pass_lds_bytes<PREC, 2>(1));
 }
 
-// the outputs each precision's passes use: its own type, the FP64 first solve, the final update
+// the outputs each precision's passes use: its own type and the final update
 template <int PREC>
 hipError_t allow_wide() {
   constexpr int OWN = PREC == PREC_F64 ? OUT_F64 : OUT_F32;
   hipError_t e = allow_wide_out<PREC, OWN>();
-  if (e == hipSuccess && OWN != OUT_F64) e = allow_wide_out<PREC, OUT_F64>();
   if (e == hipSuccess) e = allow_wide_out<PREC, OUT_FINAL>();
   return e;
 }
@@ -910,8 +917,8 @@ int plan2d_create(const ridc_problem* p, double h, double* const* ring, const in
         void* outs[4] = {L.lo1, L.lo0, L.lo1, nullptr};
         E.A = ins[kk];
         E.C = outs[kk];
-        if (k == 3) E.C = L.x64;             // first solve, stored FP64
-        if (k == 7) E.add = L.x64;           // x = x1 + S~(rho)
+        if (k == 3) E.C = L.x64;             // first solve, kept in FP32 in this buffer
+        if (k == 7) E.add = (const float*)L.x64;   // x = x1 + S~(rho)
       }
     }
   }
@@ -951,7 +958,7 @@ void run_stages(int prec, const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nma
     launch_pass<PREC_F32, OUT_F32>(d + 0 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_F32, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_F32, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F32, OUT_F64>(d + 3 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 3 * cnt, lv, cnt, nmax, s, st);
     hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, cnt), dim3(256), 0, st, lv, s);
     launch_pass<PREC_F32, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_F32, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, st);
@@ -961,7 +968,7 @@ void run_stages(int prec, const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nma
     launch_pass<PREC_BF16, OUT_F32>(d + 0 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_BF16, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_BF16, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_F64>(d + 3 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 3 * cnt, lv, cnt, nmax, s, st);
     hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, cnt), dim3(256), 0, st, lv, s);
     launch_pass<PREC_BF16, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_BF16, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, st);
