@@ -39,14 +39,14 @@ KERNEL_SOURCE = {
     "2d": os.path.join(ROOT, "paper_1209_4297_amd", "csrc", "kernels_2d.hip"),
 }
 MEASURED_TRAFFIC = {
-    ("reacdiff1d", (1024, 128, 1)): ("1d", "a1984401034a7e56", 4536320),
-    ("batched1d", (512, 1536)): ("1d", "a1984401034a7e56", 74555392),
-    ("reacdiff2d_rhs", "fp64"): ("2d", "2c0568b454154fcf", 174545920),
-    ("reacdiff2d", "fp64"): ("2d", "2c0568b454154fcf", 100908237),
-    ("reacdiff2d_rhs", "fp32"): ("2d", "2c0568b454154fcf", 193864090),
-    ("reacdiff2d", "fp32"): ("2d", "2c0568b454154fcf", 50575155),
-    ("reacdiff2d_rhs", "bf16x3"): ("2d", "2c0568b454154fcf", 193878835),
-    ("reacdiff2d", "bf16x3"): ("2d", "2c0568b454154fcf", 50569011),
+    ("reacdiff1d", (1024, 128, 1)): ("1d", "5ceb05d805782d8f", 4555776),
+    ("batched1d", (256, 1536)): ("1d", "5ceb05d805782d8f", 74679091),
+    ("reacdiff2d_rhs", "fp64"): ("2d", "2631bea0663988f9", 174561894),
+    ("reacdiff2d", "fp64"): ("2d", "2631bea0663988f9", 100910285),
+    ("reacdiff2d_rhs", "fp32"): ("2d", "2631bea0663988f9", 193867571),
+    ("reacdiff2d", "fp32"): ("2d", "2631bea0663988f9", 50575155),
+    ("reacdiff2d_rhs", "bf16x3"): ("2d", "2631bea0663988f9", 193845248),
+    ("reacdiff2d", "bf16x3"): ("2d", "2631bea0663988f9", 50573107),
 }
 
 
