@@ -39,14 +39,16 @@ KERNEL_SOURCE = {
     "2d": os.path.join(ROOT, "paper_1209_4297_amd", "csrc", "kernels_2d.hip"),
 }
 MEASURED_TRAFFIC = {
-    ("reacdiff1d", (1024, 128, 1)): ("1d", "5ceb05d805782d8f", 4555776),
-    ("batched1d", (256, 1536)): ("1d", "5ceb05d805782d8f", 74679091),
-    ("reacdiff2d_rhs", "fp64"): ("2d", "2631bea0663988f9", 174561894),
-    ("reacdiff2d", "fp64"): ("2d", "2631bea0663988f9", 100910285),
-    ("reacdiff2d_rhs", "fp32"): ("2d", "2631bea0663988f9", 193867571),
-    ("reacdiff2d", "fp32"): ("2d", "2631bea0663988f9", 50575155),
-    ("reacdiff2d_rhs", "bf16x3"): ("2d", "2631bea0663988f9", 193845248),
-    ("reacdiff2d", "bf16x3"): ("2d", "2631bea0663988f9", 50573107),
+    ("reacdiff1d", (1024, 128, 1)): ("1d", "564458ee427cc4d1", 4530176),
+    ("reacdiff1d", (1024, 128, 0)): ("1d", "564458ee427cc4d1", 4530176),
+    ("batched1d", (256, 1536)): ("1d", "564458ee427cc4d1", 72678016),
+    ("batched1d", (512, 1536)): ("1d", "564458ee427cc4d1", 72604672),
+    ("reacdiff2d_rhs", "fp64"): ("2d", "9e8239eb2a891b9e", 185633536),
+    ("reacdiff2d", "fp64"): ("2d", "9e8239eb2a891b9e", 100910336),
+    ("reacdiff2d_rhs", "fp32"): ("2d", "9e8239eb2a891b9e", 202847232),
+    ("reacdiff2d", "fp32"): ("2d", "9e8239eb2a891b9e", 50575104),
+    ("reacdiff2d_rhs", "bf16x3"): ("2d", "9e8239eb2a891b9e", 202896256),
+    ("reacdiff2d", "bf16x3"): ("2d", "9e8239eb2a891b9e", 50583296),
 }
 
 
@@ -88,6 +90,9 @@ def parse():
                     help="override the number of time steps (short runs for counter profiling)")
     ap.add_argument("--tile", default=None,
                     help="1D tiling 'threads,rows,flags' instead of autotuning (rows 0 = whole cycle)")
+    ap.add_argument("--batch-tile", default=None,
+                    help="batched 1D: grouped-launch tiling 'threads,rows' instead of autotuning "
+                         "(rows 0 = whole cycles)")
     return ap.parse_args()
 
 
@@ -312,7 +317,11 @@ def bench_batched(args, torch, ridc):
         solvers.append(s)
         u0s.append(torch.tensor(u0, dtype=torch.float64, device="cuda"))
         uTs.append(torch.empty_like(u0s[-1]))
-    batch_tile = ridc.autotune_batch(solvers)           # measured grouped-launch tiling
+    if args.batch_tile:
+        batch_tile = tuple(int(x) for x in args.batch_tile.split(","))
+        ridc.set_batch_tile(*batch_tile)
+    else:
+        batch_tile = ridc.autotune_batch(solvers)       # measured grouped-launch tiling
     nts = [p["nt"] for p, _ in cases]
     for _ in range(warmup):
         ridc.integrate_batch(solvers, u0s, nts, uTs)

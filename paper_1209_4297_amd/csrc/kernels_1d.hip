@@ -29,6 +29,20 @@ namespace ridc {
 
 namespace {
 
+// Global-memory views of descriptor pointers.  Pointers read from a launch table carry no
+// address space, so the compiler would emit flat instructions, which also count against the LDS
+// wait counter (every LDS wait would then wait for the outstanding global loads too).
+typedef __attribute__((address_space(1))) double gdbl;
+typedef __attribute__((address_space(1))) int gint;
+template <typename X>
+__device__ __forceinline__ __attribute__((address_space(1))) X* gp(X* p) {
+  return (__attribute__((address_space(1))) X*)p;
+}
+template <typename X>
+__device__ __forceinline__ const __attribute__((address_space(1))) X* gp(const X* p) {
+  return (const __attribute__((address_space(1))) X*)p;
+}
+
 // One PCR update of a row: c - g (a + b), with one rounding of the product-sum (every path
 // uses this so that all tilings give the same bits).
 __device__ __forceinline__ double pcr_upd(double c, double a, double b, double g) {
@@ -52,9 +66,9 @@ __device__ __forceinline__ double fe_eval(int fe, double ce, double um, double u
 // J is a template parameter so the window lives in registers.
 template <int J>
 struct Step {
-  const double* u;
-  double* out;
-  const double* v[J + 1];
+  const gdbl* u;
+  gdbl* out;
+  const gdbl* v[J + 1];
   double cf[J + 1], cl[J + 1];
 };
 
@@ -149,16 +163,16 @@ __device__ __forceinline__ void rhs_rows(const Geo& G, const Step<J>& S, int gba
 // Everything one level step reads besides the rings: built from a descriptor table entry
 // (batched launches) or from the kernel arguments (a single instance's launch).
 struct View {
-  double* own;
-  const double* prev;
-  const double* W;
-  const double* gamma;
-  const int* shift;
+  gdbl* own;
+  const gdbl* prev;
+  const gdbl* W;
+  const gdbl* gamma;
+  const gint* shift;
   int R_own, R_prev, n, M, bc, fe, stages, wrap, B, H;
   double dt, ce, nu_h2, inv_divisor;
 };
 
-__device__ __forceinline__ void store_row(double* p, double v, bool nt) {
+__device__ __forceinline__ void store_row(gdbl* p, double v, bool nt) {
   if (nt)
     __builtin_nontemporal_store(v, p);
   else
@@ -181,7 +195,7 @@ __device__ __forceinline__ void make_step(const View& L, int64_t m, Geo& G, Step
   S.out = L.own + (m % L.R_own) * (int64_t)n;
   if constexpr (J > 0) {
     const int64_t s = m - J > 0 ? m - J : 0;          // window t_s..t_{s+J}
-    const double* w = L.W + (nidx - s) * (J + 1);     // row r = n - s
+    const gdbl* w = L.W + (nidx - s) * (J + 1);       // row r = n - s
     const int R = L.R_prev;
     int slot = (int)(s % R);
 #pragma unroll
@@ -206,11 +220,11 @@ __device__ __forceinline__ void level_step(const View& L, int chunk, int64_t m, 
   const bool per = G.per;
   const int stages = L.stages;
   const double inv_div = L.inv_divisor;
-  const double* __restrict__ gam = L.gamma;
+  const gdbl* __restrict__ gam = L.gamma;
 
   if (L.wrap) {
     const int ms = per ? n : n + 2;                   // stored rows of the cycle
-    const int* __restrict__ shift = L.shift;
+    const gint* __restrict__ shift = L.shift;
     double* d0 = lds;
     double* d1 = lds + ms;
     rhs_rows<J>(G, S, 0, ms, d0, threadIdx.x >> 6, T / 64, threadIdx.x & 63);
@@ -325,7 +339,8 @@ __global__ __launch_bounds__(T) void k_step1d(const Lvl1D* __restrict__ items,
   const int j = L->j;
   const int64_t m = sigma - L->sigma0 - (int64_t)j * (j + 1) / 2;  // time index computed now
   if (m < 1 || m > L->nt) return;                                   // level idle this step
-  View v{L->own, L->prev, L->W, L->gamma, L->shift, L->R_own, L->R_prev, L->n, L->M, L->bc,
+  View v{gp(L->own), gp(L->prev), gp(L->W), gp(L->gamma), gp(L->shift), L->R_own, L->R_prev,
+         L->n, L->M, L->bc,
          L->fe, L->stages, L->wrap, L->B, L->H, L->dt, L->ce, L->nu_h2, L->inv_divisor};
   dispatch_level<T, MJ>(j, v, bk.chunk, m, lds, false);
 }
@@ -339,7 +354,8 @@ __global__ __launch_bounds__(T) void k_step1d_solo(const Solo1D a, int64_t sigma
   const int chunk = blockIdx.x - j * a.nchunks;
   const int64_t m = sigma - (int64_t)j * (j + 1) / 2;
   if (m < 1 || m > a.nt) return;
-  View v{a.ring[j], j > 0 ? a.ring[j - 1] : nullptr, a.W[j], a.gamma, a.shift, a.R[j],
+  View v{gp(a.ring[j]), gp(j > 0 ? a.ring[j - 1] : nullptr), gp(a.W[j]), gp(a.gamma),
+         gp(a.shift), a.R[j],
          j > 0 ? a.R[j - 1] : 1, a.n, a.M, a.bc, a.fe, a.stages, a.wrap, a.B, a.H, a.dt,
          a.ce, a.nu_h2, a.inv_divisor};
   dispatch_level<T, MJ>(j, v, chunk, m, lds, a.nt_store != 0);
@@ -397,7 +413,8 @@ __device__ __forceinline__ void fused_body(const Fused1D& F) {
   double* d1 = d0 + ms;
   View v{};
   if (mine) {
-    v = View{F.ring[j], j > 0 ? F.ring[j - 1] : nullptr, F.W[j], F.gamma, F.shift, F.R[j],
+    v = View{gp(F.ring[j]), gp(j > 0 ? F.ring[j - 1] : nullptr), gp(F.W[j]), gp(F.gamma),
+             gp(F.shift), F.R[j],
              j > 0 ? F.R[j - 1] : 1, n, M, F.bc, F.fe, F.stages, 1, 0, 0, F.dt, F.ce, F.nu_h2,
              F.inv_divisor};
     // Dirichlet ghost rows (0 and n+1) must read zero in both buffers whatever their roles: a
@@ -414,8 +431,8 @@ __device__ __forceinline__ void fused_body(const Fused1D& F) {
     if (act) fused_rhs_any<MJ>(j, v, m, d0, lt, G);
     __syncthreads();
     for (int k = 0; k < stages; ++k) {
-      const int sh = F.shift[k];
-      const double g = F.gamma[k];
+      const int sh = gp(F.shift)[k];
+      const double g = gp(F.gamma)[k];
       if (act) {
         constexpr int RB = 4;                 // rows gathered together
 #pragma unroll 1
@@ -453,7 +470,7 @@ __device__ __forceinline__ void fused_body(const Fused1D& F) {
       d1 = t;
     }
     if (act) {
-      double* out = F.ring[j] + (m % F.R[j]) * (int64_t)n;
+      gdbl* out = gp(F.ring[j]) + (m % F.R[j]) * (int64_t)n;
       for (int l = l0 + lt; l < l1; l += G) out[per ? l : l - 1] = d0[l] * F.inv_divisor;
     }
     __syncthreads();                         // this step's values before the next step reads
@@ -488,8 +505,8 @@ __global__ void k_copy_items(const CopyItem* __restrict__ items) {
   int bad = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < it.n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = it.src[i];
-    it.dst[i] = v;
+    const double v = gp(it.src)[i];
+    gp(it.dst)[i] = v;
     if (!(v - v == 0.0)) bad = 1;      // NaN or Inf
   }
   if (it.flag && __any(bad) && (threadIdx.x & 63) == 0) atomicOr(it.flag, 1);

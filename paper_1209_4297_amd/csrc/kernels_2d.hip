@@ -104,82 +104,238 @@ __device__ __forceinline__ double fe2(int fe, double u) {
   return fe == RIDC_FE_LOGISTIC ? u * (1.0 - u) : 0.0;
 }
 
+// Loads and stores through pointers read from the launch tables.  The compiler cannot tell
+// their address space and would emit flat instructions, which also count against the LDS wait
+// counter (every LDS wait would then wait for the outstanding global loads too); these name the
+// global space.
 template <typename V>
-__device__ __forceinline__ double lap5(const V* __restrict__ v, int iy, int ix, int n) {
-  const int64_t c = (int64_t)iy * n + ix;
-  const double w = ix > 0 ? (double)v[c - 1] : 0.0;
-  const double e = ix < n - 1 ? (double)v[c + 1] : 0.0;
-  const double s = iy > 0 ? (double)v[c - n] : 0.0;
-  const double no = iy < n - 1 ? (double)v[c + n] : 0.0;
-  return ((w + e) + (s + no)) - 4.0 * (double)v[c];
+__device__ __forceinline__ V gld(const void* p) {
+  return *(const __attribute__((address_space(1))) V*)p;
+}
+template <typename V>
+__device__ __forceinline__ void gst(void* p, V v) {
+  *(__attribute__((address_space(1))) V*)p = v;
 }
 
 // The reduced-precision paths keep their intermediates in FP32; the split-BF16 pass splits its
 // A operand into BF16 (hi, lo) while staging it.
 __device__ __forceinline__ void store_lo(void* base, int64_t idx, double v) {
-  ((float*)base)[idx] = (float)v;
+  gst<float>((float*)base + idx, (float)v);
 }
 
 // ---------------------------------------------------------------------------------------------
-// right-hand side (increment form), FP64; also writes the low-precision copy
+// stencil kernels: a wave owns 64 columns of ST_RY consecutive rows and walks down them, keeping
+// the rows above and below in registers, so each stencil vector is read once per point.  Column
+// neighbours come from the adjacent lanes (DPP wave shifts); lanes 0 and 63 load the columns
+// just outside the wave's 64.  Columns at or beyond n hold zero, which is also the Dirichlet
+// ghost value, so a wave that straddles the last column needs no special case.
 // ---------------------------------------------------------------------------------------------
+constexpr int ST_RY = 16;    // rows per wave
+constexpr int ST_WAVES = 4;  // waves per block, stacked in rows
+
+__device__ __forceinline__ double lane_below(double v) {   // lane l gets lane l-1's v (lane 0: 0)
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_above(double v) {   // lane l gets lane l+1's v (lane 63: 0)
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_below(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_above(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
+// Where a block's wave sits: the first row and column it owns, or false when it owns none.
+__device__ __forceinline__ bool stencil_tile(int n, int* iy0, int* ix0) {
+  *ix0 = blockIdx.x * 64;
+  *iy0 = (blockIdx.y * ST_WAVES + (threadIdx.x >> 6)) * ST_RY;
+  return *ix0 < n && *iy0 < n;
+}
+
+// Column neighbours of a row value held one per lane: from the adjacent lanes, and for lanes 0
+// and 63 from `edge(column)` (zero outside the grid).
+template <typename T, typename Edge>
+__device__ __forceinline__ void column_neighbours(T mid, int ix0, int n, Edge edge, double* w,
+                                                  double* e) {
+  const int lane = threadIdx.x & 63;
+  *w = (double)lane_below(mid);
+  *e = (double)lane_above(mid);
+  if (lane == 0 && ix0 > 0) *w = (double)edge(ix0 - 1);
+  if (lane == 63 && ix0 + 64 < n) *e = (double)edge(ix0 + 64);
+}
+
+// ---------------------------------------------------------------------------------------------
+// right-hand side (increment form), FP64; also writes the low-precision copy.  The quadrature
+// of f along level j-1 is taken as sum_i w_i f_E(v_i) + nu Lap_h (sum_i w_i v_i): the stencil
+// is linear, so one stencil of the weighted window replaces j+1 stencils.
+// ---------------------------------------------------------------------------------------------
+// The values of one grid row that the right-hand side needs at a column.
+struct RhsRow {
+  double V;     // sum_i w_i v_i (level 0: the own value u)
+  double fq;    // sum_i w_i f_E(v_i) (level 0: f_E(u))
+  double fen;   // f_E(v at node n)
+  double vn1;   // v at node n+1
+  double u;     // own value at node n
+};
+
+// JT = the number of window vectors j + 1 when it is fixed at compile time (0 for the
+// predictor), or -1: any j, up to the largest order.  This kernel uses no LDS, and its plain
+// (flat) loads measured faster than global ones (31.2 against 33.2 us per launch at 1024^2,
+// FP64).
+template <int JT>
+__device__ __forceinline__ void rhs_level(const Lvl2D& L, int64_t m, int iy0, int ix0) {
+  constexpr int JN = JT < 0 ? RIDC_MAX_ORDER : (JT == 0 ? 1 : JT);
+  const int n = L.n;
+  const int ix = ix0 + (threadIdx.x & 63);
+  const bool col = ix < n;
+  const int64_t nn = (int64_t)n * n;
+  const int64_t nidx = m - 1;
+  const double* __restrict__ u = L.own + (nidx % L.R_own) * nn;
+  const int nv = JT < 0 ? L.j + 1 : JT;        // window vectors
+  const double* __restrict__ vp[JN];
+  double w[JN];
+  int rn = 0;                                  // window index of node n (node n+1 is rn + 1)
+  if (JT == 0) {
+    vp[0] = u;
+    w[0] = 1.0;
+  } else {
+    const int64_t s = m - L.j > 0 ? m - L.j : 0;
+    rn = (int)(nidx - s);
+#pragma unroll
+    for (int i = 0; i < JN; ++i) {
+      if (i < nv) {
+        vp[i] = L.prev + ((s + i) % L.R_prev) * nn;
+        w[i] = gld<double>(L.W + (nidx - s) * (L.j + 1) + i);
+      }
+    }
+  }
+  auto window_sum = [&](int64_t c) {           // sum_i w_i v_i at one point
+    if (JT == 0) return u[c];
+    double V = 0.0;
+#pragma unroll
+    for (int i = 0; i < JN; ++i)
+      if (i < nv) V += w[i] * vp[i][c];
+    return V;
+  };
+  auto load = [&](int iy) {
+    RhsRow r{0.0, 0.0, 0.0, 0.0, 0.0};
+    if (iy < 0 || iy >= n || !col) return r;
+    const int64_t c = (int64_t)iy * n + ix;
+    if (JT == 0) {
+      r.u = u[c];
+      r.V = r.u;
+      r.fq = fe2(L.fe, r.u);
+      return r;
+    }
+    r.u = u[c];
+#pragma unroll
+    for (int i = 0; i < JN; ++i) {
+      if (i < nv) {
+        const double v = vp[i][c];
+        const double f = fe2(L.fe, v);
+        r.V += w[i] * v;
+        r.fq += w[i] * f;
+        if (i == rn) r.fen = f;
+        if (i == rn + 1) r.vn1 = v;
+      }
+    }
+    return r;
+  };
+  const double dt = L.dt;
+  double up = load(iy0 - 1).V;
+  RhsRow mid = load(iy0);
+  const int rows = n - iy0 < ST_RY ? n - iy0 : ST_RY;
+  for (int r = 0; r < rows; ++r) {
+    const int iy = iy0 + r;
+    const RhsRow dn = load(iy + 1);
+    double vw, ve;
+    column_neighbours(mid.V, ix0, n, [&](int x) { return window_sum((int64_t)iy * n + x); }, &vw,
+                      &ve);
+    const double lap = ((vw + ve) + (up + dn.V)) - 4.0 * mid.V;
+    const double quad = mid.fq + L.nu_h2 * lap;
+    const double b = JT == 0 ? dt * quad
+                             : (mid.u - mid.vn1) + dt * quad + dt * (fe2(L.fe, mid.u) - mid.fen);
+    if (col) {
+      const int64_t c = (int64_t)iy * n + ix;
+      L.b64[c] = b;
+      if (L.prec != PREC_F64) store_lo(L.lo0, c, b);
+    }
+    up = mid.V;
+    mid = dn;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_rhs2d(const Lvl2D* __restrict__ levels, int64_t sigma) {
   const Lvl2D& L = levels[blockIdx.z];
   int64_t m;
   if (!level_active(L, sigma, &m)) return;
-  const int n = L.n;
-  const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (ix >= n || iy >= n) return;
-  const int64_t nn = (int64_t)n * n;
-  const int64_t c = (int64_t)iy * n + ix;
-  const int64_t nidx = m - 1;
-  const double* u = L.own + (nidx % L.R_own) * nn;
-  const double dt = L.dt;
-  double b;
-  if (L.j == 0) {
-    b = dt * (fe2(L.fe, u[c]) + L.nu_h2 * lap5(u, iy, ix, n));
-  } else {
-    const int j = L.j;
-    const int64_t s = m - j > 0 ? m - j : 0;
-    const double* w = L.W + (nidx - s) * (j + 1);
-    double quad = 0.0, fe_n = 0.0, v_n1 = 0.0;
-    for (int i = 0; i <= j; ++i) {
-      const int64_t node = s + i;
-      const double* v = L.prev + (node % L.R_prev) * nn;
-      const double v0 = v[c];
-      const double fev = fe2(L.fe, v0);
-      quad += w[i] * (fev + L.nu_h2 * lap5(v, iy, ix, n));
-      if (node == nidx) fe_n = fev;
-      if (node == nidx + 1) v_n1 = v0;
-    }
-    const double u0 = u[c];
-    b = (u0 - v_n1) + dt * quad + dt * (fe2(L.fe, u0) - fe_n);
-  }
-  if (L.prec == PREC_F64) {
-    L.b64[c] = b;
-  } else {
-    L.b64[c] = b;
-    store_lo(L.lo0, c, b);
+  int iy0, ix0;
+  if (!stencil_tile(L.n, &iy0, &ix0)) return;
+  switch (L.j) {
+    case 0: rhs_level<0>(L, m, iy0, ix0); break;
+    case 1: rhs_level<2>(L, m, iy0, ix0); break;
+    case 2: rhs_level<3>(L, m, iy0, ix0); break;
+    case 3: rhs_level<4>(L, m, iy0, ix0); break;
+    default: rhs_level<-1>(L, m, iy0, ix0); break;
   }
 }
 
-// rho = b - (x1 - dt nu Lap_h x1), FP64, written in low precision
+// rho = b - (x1 - dt nu Lap_h x1), FP64, written in low precision.  The first solve x1 is held in
+// FP32 (in the x64 buffer; it leaves an FP32 accumulator, so nothing is lost).  Every row of the
+// wave's column strip is loaded before any is used, so all of a wave's loads are in flight at
+// once.
 __global__ __launch_bounds__(256) void k_resid2d(const Lvl2D* __restrict__ levels, int64_t sigma) {
   const Lvl2D& L = levels[blockIdx.z];
   int64_t m;
   if (!level_active(L, sigma, &m)) return;
   const int n = L.n;
-  const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (ix >= n || iy >= n) return;
-  const int64_t c = (int64_t)iy * n + ix;
-  // the first solve x1 is held in FP32 (in the x64 buffer; it leaves an FP32 accumulator, so
-  // nothing is lost), the residual is formed in FP64
-  const float* x1 = (const float*)L.x64;
-  const double x = x1[c];
-  const double rho = L.b64[c] - (x - L.dt * L.nu_h2 * lap5(x1, iy, ix, n));
-  store_lo(L.lo0, c, rho);
+  int iy0, ix0;
+  if (!stencil_tile(n, &iy0, &ix0)) return;
+  const int lane = threadIdx.x & 63;
+  const int ix = ix0 + lane;
+  const bool col = ix < n;
+  const float* __restrict__ x1 = (const float*)L.x64;
+  // the column just outside the strip that lanes 0 and 63 supply, if it is inside the grid
+  const int ex = lane == 0 ? ix0 - 1 : ix0 + 64;
+  const bool edge = (lane == 0 && ix0 > 0) || (lane == 63 && ix0 + 64 < n);
+  float xr[ST_RY + 2], xe[ST_RY];
+  double br[ST_RY];
+#pragma unroll
+  for (int r = 0; r < ST_RY + 2; ++r) {
+    const int iy = iy0 - 1 + r;
+    xr[r] = iy >= 0 && iy < n && col ? gld<float>(x1 + (int64_t)iy * n + ix) : 0.0f;
+  }
+#pragma unroll
+  for (int r = 0; r < ST_RY; ++r) {
+    const int iy = iy0 + r;
+    const bool in = iy < n;
+    br[r] = in && col ? gld<double>(L.b64 + (int64_t)iy * n + ix) : 0.0;
+    xe[r] = in && edge ? gld<float>(x1 + (int64_t)iy * n + ex) : 0.0f;
+  }
+#pragma unroll
+  for (int r = 0; r < ST_RY; ++r) {
+    const int iy = iy0 + r;
+    if (iy >= n) break;
+    double xw = (double)lane_below(xr[r + 1]), xa = (double)lane_above(xr[r + 1]);
+    if (lane == 0) xw = (double)xe[r];
+    if (lane == 63) xa = (double)xe[r];
+    const double x = (double)xr[r + 1];
+    const double lap = ((xw + xa) + ((double)xr[r] + (double)xr[r + 2])) - 4.0 * x;
+    if (col) store_lo(L.lo0, (int64_t)iy * n + ix, br[r] - (x - L.dt * L.nu_h2 * lap));
+  }
+}
+
+// one launch of a stencil kernel over `cnt` levels of sides up to nmax
+static void launch_stencil(void (*k)(const Lvl2D*, int64_t), const Lvl2D* lv, int cnt, int64_t nmax,
+                    int64_t sigma, hipStream_t st) {
+  const unsigned gx = (unsigned)((nmax + 63) / 64);
+  const unsigned gy = (unsigned)((nmax + ST_RY * ST_WAVES - 1) / (ST_RY * ST_WAVES));
+  hipLaunchKernelGGL(k, dim3(gx, gy, cnt), dim3(64 * ST_WAVES), 0, st, lv, sigma);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -350,9 +506,9 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       const int ga = row0 + r;
       const int64_t ko = k0 + q * EA;
       const TA* arow = A + (int64_t)ga * n;
-      S.ra[c] = ga < n ? *(const u32x4*)(arow + ko) : u32x4{0, 0, 0, 0};
+      S.ra[c] = ga < n ? gld<u32x4>(arow + ko) : u32x4{0, 0, 0, 0};
       if constexpr (FOLD)
-        S.rm[c] = ga < n ? *(const u32x4*)(arow + (n - ko - EA)) : u32x4{0, 0, 0, 0};
+        S.rm[c] = ga < n ? gld<u32x4>(arow + (n - ko - EA)) : u32x4{0, 0, 0, 0};
     }
 #pragma unroll
     for (int s = 0; s < NSPLIT; ++s)
@@ -362,7 +518,7 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
         const int r = id / CH, q = id % CH;
         const int gb = col0 + r;                        // Q symmetric: row j of Q = column j
         const int64_t ko = k0 + q * E16;
-        S.rb[s][c] = gb < n ? *(const u32x4*)(Q + s * qsplit + (int64_t)gb * K + ko)
+        S.rb[s][c] = gb < n ? gld<u32x4>(Q + s * qsplit + (int64_t)gb * K + ko)
                             : u32x4{0, 0, 0, 0};
       }
   };
@@ -594,8 +750,8 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       const int64_t o = (int64_t)j * n + i0;
 #pragma unroll
       for (int e = 0; e < ET / 2; ++e) {
-        bq[slot][e] = *(const dbl2*)(base + o + 2 * e);
-        aq[slot][e] = E.add ? *(const flt2*)(E.add + o + 2 * e) : flt2{0.0f, 0.0f};
+        bq[slot][e] = gld<dbl2>(base + o + 2 * e);
+        aq[slot][e] = E.add ? gld<flt2>(E.add + o + 2 * e) : flt2{0.0f, 0.0f};
       }
     }
   };
@@ -646,24 +802,24 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       }
     }
     if (E.divide) {
-      const double lj = E.lam[j];
+      const double lj = gld<double>(E.lam + j);
 #pragma unroll
-      for (int e = 0; e < ET; ++e) v[e] = v[e] / (1.0 + (E.lam[i0 + e] + lj));
+      for (int e = 0; e < ET; ++e) v[e] = v[e] / (1.0 + (gld<double>(E.lam + i0 + e) + lj));
     }
     if constexpr (OUT == OUT_F64) {
 #pragma unroll
-      for (int e = 0; e < ET; e += 2) *(dbl2*)((double*)E.C + o + e) = dbl2{v[e], v[e + 1]};
+      for (int e = 0; e < ET; e += 2) gst<dbl2>((double*)E.C + o + e, dbl2{v[e], v[e + 1]});
     } else if constexpr (OUT == OUT_F32) {
 #pragma unroll
       for (int e = 0; e < ET; e += 4)
-        *(flt4*)((float*)E.C + o + e) =
-            flt4{(float)v[e], (float)v[e + 1], (float)v[e + 2], (float)v[e + 3]};
+        gst<flt4>((float*)E.C + o + e,
+                  flt4{(float)v[e], (float)v[e + 1], (float)v[e + 2], (float)v[e + 3]});
     } else {
 #pragma unroll
       for (int e = 0; e < ET; e += 2) {
         const dbl2 bs = bq[cur][e / 2];
         const dbl2 ad = dbl2{(double)aq[cur][e / 2][0], (double)aq[cur][e / 2][1]};
-        *(dbl2*)(out64 + o + e) = dbl2{bs[0] + (ad[0] + v[e]), bs[1] + (ad[1] + v[e + 1])};
+        gst<dbl2>(out64 + o + e, dbl2{bs[0] + (ad[0] + v[e]), bs[1] + (ad[1] + v[e + 1])});
       }
     }
   }
@@ -947,8 +1103,7 @@ namespace {
 // passes is pass-major: passes[k * cnt + e].
 void run_stages(int prec, const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nmax, int64_t s,
                 hipStream_t st) {
-  const unsigned gx = (unsigned)((nmax + 63) / 64), gy = (unsigned)((nmax + 3) / 4);
-  hipLaunchKernelGGL(k_rhs2d, dim3(gx, gy, cnt), dim3(256), 0, st, lv, s);
+  launch_stencil(k_rhs2d, lv, cnt, nmax, s, st);
   if (prec == PREC_F64) {
     launch_pass<PREC_F64, OUT_F64>(d + 0 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_F64, OUT_F64>(d + 1 * cnt, lv, cnt, nmax, s, st);
@@ -959,7 +1114,7 @@ void run_stages(int prec, const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nma
     launch_pass<PREC_F32, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_F32, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_F32, OUT_F32>(d + 3 * cnt, lv, cnt, nmax, s, st);
-    hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, cnt), dim3(256), 0, st, lv, s);
+    launch_stencil(k_resid2d, lv, cnt, nmax, s, st);
     launch_pass<PREC_F32, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_F32, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_F32, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, st);
@@ -969,7 +1124,7 @@ void run_stages(int prec, const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nma
     launch_pass<PREC_BF16, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_BF16, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_BF16, OUT_F32>(d + 3 * cnt, lv, cnt, nmax, s, st);
-    hipLaunchKernelGGL(k_resid2d, dim3(gx, gy, cnt), dim3(256), 0, st, lv, s);
+    launch_stencil(k_resid2d, lv, cnt, nmax, s, st);
     launch_pass<PREC_BF16, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_BF16, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, st);
     launch_pass<PREC_BF16, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, st);
@@ -1106,9 +1261,8 @@ int plan2d_advance(Plan2D* const* pls, int count, const int64_t* sigma_before, i
 int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us) {
   const int P = pl->P;
   const int64_t n = pl->n;
-  const unsigned gx = (unsigned)((n + 63) / 64), gy = (unsigned)((n + 3) / 4);
   // inputs of the first pass of this step, then `reps` back-to-back launches of that pass
-  hipLaunchKernelGGL(k_rhs2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, sigma);
+  launch_stencil(k_rhs2d, pl->d_levels, P, n, sigma, stream);
   hipEvent_t a, b;
   RIDC_HIP_TRY(hipEventCreate(&a));
   RIDC_HIP_TRY(hipEventCreate(&b));
@@ -1138,15 +1292,14 @@ int plan2d_time_rhs(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, dou
                     double* bytes) {
   const int P = pl->P;
   const int64_t n = pl->n;
-  const unsigned gx = (unsigned)((n + 63) / 64), gy = (unsigned)((n + 3) / 4);
   // the right-hand side of this step, launched repeatedly (it rewrites the same values)
-  hipLaunchKernelGGL(k_rhs2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, sigma);
+  launch_stencil(k_rhs2d, pl->d_levels, P, n, sigma, stream);
   hipEvent_t a, b;
   RIDC_HIP_TRY(hipEventCreate(&a));
   RIDC_HIP_TRY(hipEventCreate(&b));
   (void)hipEventRecord(a, stream);
   for (int r = 0; r < reps; ++r)
-    hipLaunchKernelGGL(k_rhs2d, dim3(gx, gy, P), dim3(256), 0, stream, pl->d_levels, sigma);
+    launch_stencil(k_rhs2d, pl->d_levels, P, n, sigma, stream);
   (void)hipEventRecord(b, stream);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipEventSynchronize(b);

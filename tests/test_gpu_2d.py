@@ -56,7 +56,7 @@ def oracle2d(prob, u0, nt=None):
 
 
 @pytest.mark.parametrize("n,nt,order", [(64, 40, 4), (96, 30, 4), (256, 20, 4), (160, 12, 3),
-                                        (32, 8, 1), (64, 6, 6)])
+                                        (32, 8, 1), (64, 6, 6), (32, 20, 8)])
 def test_fp64_parity(env, n, nt, order):
     prob, u0 = workloads.config_reacdiff_2d(n=n, nt=nt, order=order, T=nt * 2e-3, nu=1e-3)
     _say(f"case: 2D fp64 n={n} nt={nt} P={order}")
