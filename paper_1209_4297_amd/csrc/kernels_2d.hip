@@ -416,15 +416,21 @@ __device__ __forceinline__ u32x4 fold1_f32(u32x4 a, u32x4 m, float sg) {
 // FOLD (n a multiple of 64): the contraction runs over k < n/2 with the folded A operands and
 // E.Q the folded transform: row j' (n rows) holds Q_{k, perm(j')} for k < n/2, perm(j') = 2j'
 // for j' < n/2 and 2(j' - n/2) + 1 above; output column j' of the block grid is column perm(j').
-// KX = 2 doubles the k-slice (one slice in flight instead of two); the operands then need more
-// than 64 KB of LDS, so every variant takes its LDS dynamically (pass_lds_bytes).
+// KX = 2 doubles the k-slice (one slice in flight instead of two).  FP32 and FP64 keep two LDS
+// stages of a k-slice (the next slice is stored while the current one feeds the matrix cores,
+// one barrier per slice); the split-BF16 operands are twice as large and keep one.  Most
+// variants need more than 64 KB, so every variant takes its LDS dynamically (pass_lds_bytes).
+template <int PREC>
+constexpr int lds_stages() {
+  return PREC == PREC_BF16 ? 1 : 2;
+}
 template <int PREC, int KX>
 constexpr size_t pass_lds_bytes(int fold) {
   typedef typename Tr<PREC>::T T;
   constexpr int BK = Tr<PREC>::BK * KX;
   constexpr int LDE = (BK * (int)sizeof(T) + 16) / (int)sizeof(T);
   constexpr int NSPLIT = PREC == PREC_BF16 ? 2 : 1;
-  return (size_t)((fold ? 2 : 1) * NSPLIT + NSPLIT) * BT * LDE * sizeof(T);
+  return (size_t)lds_stages<PREC>() * ((fold ? 2 : 1) * NSPLIT + NSPLIT) * BT * LDE * sizeof(T);
 }
 
 template <int PREC, int OUT, int FOLD, int KX>
@@ -441,9 +447,16 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   constexpr int CPT = BT * CH / NTHR;                 // chunks per thread per operand and split
   constexpr int NA = FOLD ? 2 : 1;                    // A operands: (folded sums, differences)
   extern __shared__ __attribute__((aligned(16))) unsigned char pass_smem[];
-  T (*As)[NSPLIT][BT * LDE] = reinterpret_cast<T (*)[NSPLIT][BT * LDE]>(pass_smem);
-  T (*Bs)[BT * LDE] =
-      reinterpret_cast<T (*)[BT * LDE]>(pass_smem + (size_t)NA * NSPLIT * BT * LDE * sizeof(T));
+  // LDS stage b of a k-slice: the A operands, then Q
+  constexpr size_t A_BYTES = (size_t)NA * NSPLIT * BT * LDE * sizeof(T);
+  constexpr size_t STAGE_BYTES = A_BYTES + (size_t)NSPLIT * BT * LDE * sizeof(T);
+  auto stage_a = [&](int b) {
+    return reinterpret_cast<T (*)[NSPLIT][BT * LDE]>(pass_smem + b * STAGE_BYTES);
+  };
+  auto stage_b = [&](int b) {
+    return reinterpret_cast<T (*)[BT * LDE]>(pass_smem + b * STAGE_BYTES + A_BYTES);
+  };
+  T (*As)[NSPLIT][BT * LDE] = stage_a(0);      // also the epilogue's staging area
 
   // XCD-aware tile order: workgroups go to the 8 XCDs round-robin by linear id, so tile q of
   // XCD x is x * (T / 8) + (id / 8): each XCD takes a contiguous run of tiles, and the column
@@ -546,7 +559,9 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       }
     }
   };
-  auto sstore = [&](const Slice& S) {
+  auto sstore = [&](const Slice& S, int stage) {
+    T (*As)[NSPLIT][BT * LDE] = stage_a(stage);
+    T (*Bs)[BT * LDE] = stage_b(stage);
 #pragma unroll
     for (int c = 0; c < NAC; ++c) {
       const int id = tid + c * NTHR;
@@ -604,7 +619,9 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   const int pa1 = FOLD && col0 + wn + 16 >= half ? 1 : 0;
   const int KT = K / BK;
   const int r16 = lane & 15;
-  auto mfma_slice = [&]() {
+  auto mfma_slice = [&](int stage) {
+    T (*As)[NSPLIT][BT * LDE] = stage_a(stage);
+    T (*Bs)[BT * LDE] = stage_b(stage);
     if constexpr (PREC == PREC_BF16) {
 #pragma unroll
     for (int ks = 0; ks < KX; ++ks) {
@@ -685,21 +702,36 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
           }
     }
   };
-  if constexpr (KX == 1) {
+  if constexpr (lds_stages<PREC>() == 2) {
+    // two LDS stages: slice kt + 1 is stored into the other stage (last read before the
+    // previous barrier) while slice kt feeds the matrix cores; slice kt + 2 is loading meanwhile
+    gload(sl0, 0);
+    sstore(sl0, 0);
+    if (KT > 1) gload(sl0, BK);
+    __syncthreads();
+    for (int kt = 0; kt < KT; ++kt) {
+      if (kt + 1 < KT) {
+        sstore(sl0, (kt + 1) & 1);
+        if (kt + 2 < KT) gload(sl0, (kt + 2) * BK);
+      }
+      mfma_slice(kt & 1);
+      __syncthreads();
+    }
+  } else if constexpr (KX == 1) {
     gload(sl0, 0);
     if (KT > 1) gload(sl1, BK);
     for (int kt = 0; kt < KT; kt += 2) {
       __syncthreads();
-      sstore(sl0);
+      sstore(sl0, 0);
       __syncthreads();
       if (kt + 2 < KT) gload(sl0, (kt + 2) * BK);
-      mfma_slice();
+      mfma_slice(0);
       if (kt + 1 < KT) {
         __syncthreads();
-        sstore(sl1);
+        sstore(sl1, 0);
         __syncthreads();
         if (kt + 3 < KT) gload(sl1, (kt + 3) * BK);
-        mfma_slice();
+        mfma_slice(0);
       }
     }
   } else {
@@ -707,10 +739,10 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
     gload(sl0, 0);
     for (int kt = 0; kt < KT; ++kt) {
       __syncthreads();
-      sstore(sl0);
+      sstore(sl0, 0);
       __syncthreads();
       if (kt + 1 < KT) gload(sl0, (kt + 1) * BK);
-      mfma_slice();
+      mfma_slice(0);
     }
   }
 
@@ -939,25 +971,36 @@ void launch_pass(const Pass2D* d, const Lvl2D* lv, int count, int64_t nmax, int6
   }
 }
 
-// Allow the wide-slice variants their LDS (host call, outside any stream capture).
-template <int PREC, int OUT>
-hipError_t allow_wide_out() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass2d<PREC, OUT, 1, 2>),
+// Allow the pass variants their LDS (host call, outside any stream capture).
+template <int PREC, int OUT, int FOLD, int KX>
+hipError_t allow_lds() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass2d<PREC, OUT, FOLD, KX>),
                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)pass_lds_bytes<PREC, 2>(1));
+                             (int)pass_lds_bytes<PREC, KX>(FOLD));
 }
 
-// the outputs each precision's passes use: its own type and the final update
+// every variant a precision launches: its own output type and the final update, folded or not
+// (and, split BF16, with wide slices)
+template <int PREC, int OUT>
+hipError_t allow_out() {
+  hipError_t e = allow_lds<PREC, OUT, 0, 1>();
+  if (e == hipSuccess) e = allow_lds<PREC, OUT, 1, 1>();
+  if constexpr (PREC == PREC_BF16)
+    if (e == hipSuccess) e = allow_lds<PREC, OUT, 1, 2>();
+  return e;
+}
 template <int PREC>
-hipError_t allow_wide() {
+hipError_t allow_pass() {
   constexpr int OWN = PREC == PREC_F64 ? OUT_F64 : OUT_F32;
-  hipError_t e = allow_wide_out<PREC, OWN>();
-  if (e == hipSuccess) e = allow_wide_out<PREC, OUT_FINAL>();
+  hipError_t e = allow_out<PREC, OWN>();
+  if (e == hipSuccess) e = allow_out<PREC, OUT_FINAL>();
   return e;
 }
 
 hipError_t prepare_pass_kernels(int prec) {
-  return prec == PREC_BF16 ? allow_wide<PREC_BF16>() : hipSuccess;
+  return prec == PREC_BF16  ? allow_pass<PREC_BF16>()
+         : prec == PREC_F32 ? allow_pass<PREC_F32>()
+                            : allow_pass<PREC_F64>();
 }
 
 }  // namespace
@@ -995,7 +1038,7 @@ int plan2d_create(const ridc_problem* p, double h, double* const* ring, const in
   Transform tf;
   int rc = get_transform(n, pl->prec, &tf);
   if (rc == RIDC_OK && prepare_pass_kernels(pl->prec) != hipSuccess)
-    rc = fail(RIDC_E_HIP, "wide-slice transform kernels need more LDS than the device allows");
+    rc = fail(RIDC_E_HIP, "the transform kernels need more LDS than the device allows");
   if (rc != RIDC_OK) {
     delete pl;
     return rc;
