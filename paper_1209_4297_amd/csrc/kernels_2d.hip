@@ -416,13 +416,14 @@ __device__ __forceinline__ u32x4 fold1_f32(u32x4 a, u32x4 m, float sg) {
 // FOLD (n a multiple of 64): the contraction runs over k < n/2 with the folded A operands and
 // E.Q the folded transform: row j' (n rows) holds Q_{k, perm(j')} for k < n/2, perm(j') = 2j'
 // for j' < n/2 and 2(j' - n/2) + 1 above; output column j' of the block grid is column perm(j').
-// KX = 2 doubles the k-slice (one slice in flight instead of two).  FP32 and FP64 keep two LDS
-// stages of a k-slice (the next slice is stored while the current one feeds the matrix cores,
-// one barrier per slice); the split-BF16 operands are twice as large and keep one.  Most
-// variants need more than 64 KB, so every variant takes its LDS dynamically (pass_lds_bytes).
-template <int PREC>
+// KX = 2 doubles the k-slice (one slice in flight instead of two).  A k-slice has two LDS stages
+// (the next slice is stored while the current one feeds the matrix cores, one barrier per
+// slice), except the wide split-BF16 slices, whose operands fill one stage's worth of the LDS
+// twice over.  Most variants need more than 64 KB, so every variant takes its LDS dynamically
+// (pass_lds_bytes).
+template <int PREC, int KX>
 constexpr int lds_stages() {
-  return PREC == PREC_BF16 ? 1 : 2;
+  return PREC == PREC_BF16 && KX == 2 ? 1 : 2;
 }
 template <int PREC, int KX>
 constexpr size_t pass_lds_bytes(int fold) {
@@ -430,7 +431,7 @@ constexpr size_t pass_lds_bytes(int fold) {
   constexpr int BK = Tr<PREC>::BK * KX;
   constexpr int LDE = (BK * (int)sizeof(T) + 16) / (int)sizeof(T);
   constexpr int NSPLIT = PREC == PREC_BF16 ? 2 : 1;
-  return (size_t)lds_stages<PREC>() * ((fold ? 2 : 1) * NSPLIT + NSPLIT) * BT * LDE * sizeof(T);
+  return (size_t)lds_stages<PREC, KX>() * ((fold ? 2 : 1) * NSPLIT + NSPLIT) * BT * LDE * sizeof(T);
 }
 
 template <int PREC, int OUT, int FOLD, int KX>
@@ -505,12 +506,12 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-  // global -> register staging of one k-slice (A, its mirrored columns when folding, Q); two
-  // slices are in flight, so a slice's loads have two MFMA phases to arrive
+  // global -> register staging of one k-slice (A, its mirrored columns when folding, Q); a
+  // slice's loads are issued one MFMA phase before they are stored into LDS
   struct Slice {
     u32x4 ra[NAC], rm[NAC], rb[NSPLIT][CPT];
   };
-  Slice sl0, sl1;
+  Slice sl0;
   auto gload = [&](Slice& S, int k0) {
 #pragma unroll
     for (int c = 0; c < NAC; ++c) {
@@ -702,7 +703,7 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
           }
     }
   };
-  if constexpr (lds_stages<PREC>() == 2) {
+  if constexpr (lds_stages<PREC, KX>() == 2) {
     // two LDS stages: slice kt + 1 is stored into the other stage (last read before the
     // previous barrier) while slice kt feeds the matrix cores; slice kt + 2 is loading meanwhile
     gload(sl0, 0);
@@ -716,23 +717,6 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       }
       mfma_slice(kt & 1);
       __syncthreads();
-    }
-  } else if constexpr (KX == 1) {
-    gload(sl0, 0);
-    if (KT > 1) gload(sl1, BK);
-    for (int kt = 0; kt < KT; kt += 2) {
-      __syncthreads();
-      sstore(sl0, 0);
-      __syncthreads();
-      if (kt + 2 < KT) gload(sl0, (kt + 2) * BK);
-      mfma_slice(0);
-      if (kt + 1 < KT) {
-        __syncthreads();
-        sstore(sl1, 0);
-        __syncthreads();
-        if (kt + 3 < KT) gload(sl1, (kt + 3) * BK);
-        mfma_slice(0);
-      }
     }
   } else {
     // wide slices: one in flight, its loads cover a whole MFMA phase of twice the length

@@ -56,7 +56,8 @@ def oracle2d(prob, u0, nt=None):
 
 
 @pytest.mark.parametrize("n,nt,order", [(64, 40, 4), (96, 30, 4), (256, 20, 4), (160, 12, 3),
-                                        (32, 8, 1), (64, 6, 6), (32, 20, 8)])
+                                        (32, 8, 1), (64, 6, 6), (32, 20, 8),
+                                        (192, 10, 4)])
 def test_fp64_parity(env, n, nt, order):
     prob, u0 = workloads.config_reacdiff_2d(n=n, nt=nt, order=order, T=nt * 2e-3, nu=1e-3)
     _say(f"case: 2D fp64 n={n} nt={nt} P={order}")
@@ -70,7 +71,7 @@ def test_fp64_parity(env, n, nt, order):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("n,nt", [(128, 40), (96, 20)])
+@pytest.mark.parametrize("n,nt", [(128, 40), (96, 20), (192, 10)])
 def test_mixed_precision_parity(env, prec, n, nt):
     prob, u0 = workloads.config_reacdiff_2d(n=n, nt=nt, order=4, T=nt * 2e-3, nu=1e-3)
     _say(f"case: 2D {prec} n={n} nt={nt}")
