@@ -111,8 +111,12 @@ def parse():
     return ap.parse_args()
 
 
-def oracle_time(fn):
-    """Run fn() with BLAS/FFT threads limited to one; returns (result, seconds)."""
+CPU_SAMPLE_S = 10.0      # seconds of oracle work timed for the CPU baseline
+
+
+def oracle_time(fn, min_s=CPU_SAMPLE_S):
+    """Run fn() with BLAS/FFT threads limited to one, again and again until min_s seconds have
+    passed (at least once); returns (first result, repetitions, seconds)."""
     try:
         from threadpoolctl import threadpool_limits
         limiter = threadpool_limits(limits=1)
@@ -120,10 +124,14 @@ def oracle_time(fn):
         limiter = None
     t = time.perf_counter()
     out = fn()
+    reps = 1
+    while time.perf_counter() - t < min_s:
+        fn()
+        reps += 1
     dt = time.perf_counter() - t
     if limiter is not None:
         limiter.unregister()
-    return out, dt
+    return out, reps, dt
 
 
 def run_single(args, torch, ridc, prob, u0, prec, steps, warmup, tune=True, segments=1):
@@ -232,13 +240,12 @@ def bench_1d(args, torch, ridc, which):
     cpu = rel = None
     if not args.no_cpu:
         from oracle import Problem, rel_l2, ridc_pipelined, ridc_restarted
-        reps = 20 if which == "advdiff1d" else 1
         if segments > 1:
-            ref, sec = oracle_time(lambda: ridc_restarted(Problem.from_dict(prob), u0, nt, P,
-                                                          segments))
+            ref, reps, sec = oracle_time(lambda: ridc_restarted(Problem.from_dict(prob), u0, nt,
+                                                                P, segments))
         else:
-            ref, sec = oracle_time(lambda: [ridc_pipelined(Problem.from_dict(prob), u0, nt, P)[-1]
-                                            for _ in range(reps)][-1])
+            ref, reps, sec = oracle_time(lambda: ridc_pipelined(Problem.from_dict(prob), u0, nt,
+                                                                P)[-1])
         rel = rel_l2(out, ref)
         cpu = {"value": round(n * nt * reps / sec, 1), "unit": "grid-point-steps/s", "cores": 1,
                "kind": "oracle",
@@ -315,11 +322,11 @@ def finish_2d(args, prob, u0, n, nt, P, el, steps, warmup, roof, roof_rhs, check
     if not args.no_cpu:
         from oracle import Problem, ridc_pipelined
         nts = 6
-        _, sec = oracle_time(lambda: ridc_pipelined(Problem.from_dict(prob), u0, nts, P))
-        cpu = {"value": round(n * n * nts / sec, 1), "unit": "grid-point-steps/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"the full 1024^2 grid for the first {nts} time steps of all {P} levels "
-                         f"({P * nts} level steps, {sec:.1f} s), one thread"}
+        _, reps, sec = oracle_time(lambda: ridc_pipelined(Problem.from_dict(prob), u0, nts, P))
+        cpu = {"value": round(n * n * nts * reps / sec, 1), "unit": "grid-point-steps/s",
+               "cores": 1, "kind": "oracle",
+               "sample": f"the full {n}^2 grid for the first {nts} time steps of all {P} levels, "
+                         f"{reps}x ({P * nts * reps} level steps, {sec:.1f} s), one thread"}
     desc = ("2D reaction-diffusion u_t = nu Lap u + u(1-u), Dirichlet [0,1]^2, 1024x1024, "
             f"nu=1e-4, 8 seeded bumps, RIDC order 4, T={prob['T']:g}, Nt={nt}, "
             f"transforms {args.prec}")
@@ -387,13 +394,13 @@ def bench_batched(args, torch, ridc):
         def run():
             return [ridc_pipelined(Problem.from_dict(cases[i][0]), cases[i][1], nts[i], 4)[-1]
                     for i in idx]
-        refs, sec = oracle_time(run)
+        refs, reps, sec = oracle_time(run)
         check["rel_l2_vs_oracle_max_of_sample"] = max(rel_l2(outs[i], r) for i, r in zip(idx, refs))
-        pts = sum(cases[i][0]["n"] * nts[i] for i in idx)
+        pts = sum(cases[i][0]["n"] * nts[i] for i in idx) * reps
         cpu = {"value": round(pts / sec, 1), "unit": "grid-point-steps/s", "cores": 1,
                "kind": "oracle",
                "sample": f"instances 0-3 of 256 (n = {[cases[i][0]['n'] for i in idx]}), full "
-                         f"Nt=1000, {sec:.1f} s, one thread"}
+                         f"Nt=1000, {reps}x, {sec:.1f} s, one thread"}
     desc = ("256 periodic advection-diffusion instances, N ~ U{256..4096}, a ~ U(0.5,2), "
             "nu ~ logU(1e-3,1e-1), 8 Fourier modes, RIDC order 4, Nt=1000, T=0.25, FP64")
     return dict(value=total / el, ms=1e3 * el, steps=steps, warmup=warmup, dtype="f64",
