@@ -5,6 +5,7 @@ FP64: relative L2 <= 1e-12 per level.  Reduced precision (FP32 or split-BF16 tra
 one FP64 residual refinement) has the stated tolerances below; both are far below the RIDC4
 discretisation error of these cases.
 """
+import math
 import os
 import sys
 
@@ -81,6 +82,40 @@ def test_mixed_precision_parity(env, prec, n, nt):
         err = rel_l2(lvs[j], ref[j])
         _say(f"  level {j}: rel L2 {err:.3e}")
         assert err <= TOL[prec], (j, err)
+
+
+def test_largest_side_sine_mode_closed_form(env):
+    """n = 16384, the largest 2D side (a vector is 2 GiB, so every address is 64-bit).  With no
+    explicit term a discrete sine mode is an eigenvector of the 5-point Laplacian, and order 1
+    (IMEX Euler, section II) divides it by 1 + dt nu mu each step, mu = (4/h^2)(sin^2(p pi h/2)
+    + sin^2(q pi h/2)).  Sampled against that closed form.  Rounding bound: four passes of FP64
+    sums of n/2 products, about 4 (n/2) eps = 3.6e-12 of the unit amplitude; checked at 1e-11.
+    p != q, so a transposed axis would fail."""
+    torch, ridc = env
+    n, nt, p, q, nu, T = 16384, 2, 3, 5, 0.1, 0.02
+    _say(f"case: 2D fp64 sine mode ({p},{q}) n={n} nt={nt} order 1")
+    prob = dict(dim=2, bc="dirichlet", n=n, length=1.0, fe="none", a=0.0, nu=nu, T=T, nt=nt,
+                order=1)
+    h = 1.0 / (n + 1)
+    idx = torch.arange(1, n + 1, dtype=torch.float64, device="cuda")
+    x0 = torch.outer(torch.sin(math.pi * q * h * idx), torch.sin(math.pi * p * h * idx))
+    x0 = x0.reshape(-1)                                   # row iy (mode q), column ix (mode p)
+    uT = torch.empty_like(x0)
+    s = ridc.Ridc(prob, dt=T / nt)
+    s.integrate(x0, nt, uT)
+    s.close()
+    mu = 4.0 / h**2 * (math.sin(p * math.pi * h / 2) ** 2 + math.sin(q * math.pi * h / 2) ** 2)
+    amp = (1.0 + (T / nt) * nu * mu) ** (-nt)
+    rng = np.random.default_rng(16384)
+    iy = np.concatenate([rng.integers(0, n, 2000), [0, 0, n - 1, n - 1, n // 2]])
+    ix = np.concatenate([rng.integers(0, n, 2000), [0, n - 1, 0, n - 1, n // 2]])
+    sel = torch.tensor(iy * n + ix, dtype=torch.int64, device="cuda")
+    got = uT[sel].cpu().numpy()
+    del x0, uT
+    want = amp * np.sin(math.pi * q * h * (iy + 1)) * np.sin(math.pi * p * h * (ix + 1))
+    err = float(np.max(np.abs(got - want)))
+    _say(f"  amplitude {amp:.6f}, max abs error {err:.3e}")
+    assert err <= 1e-11
 
 
 def test_zero_steps_and_fixed_point(env):
