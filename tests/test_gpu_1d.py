@@ -123,6 +123,38 @@ def test_edge_grids(env, bc, n, fe, nu, T, nt):
     check_against_oracle(env, prob, u0)
 
 
+def test_largest_system_sine_mode_closed_form(env):
+    """n = 2^28, the largest 1D system (a vector is 2 GiB; 2^21 chunks per level).  Periodic,
+    no explicit term: sin(k x) is an eigenvector of the second difference, and order 1 (IMEX
+    Euler, section II) divides it by 1 + 4 r sin^2(kh/2) each step, r = nu dt / h^2.  k = n/8,
+    so kh = pi/4 and the mode repeats every 8 rows (built from i mod 8, exact at any i).
+    Sampled against the closed form; the solve's rounding does not grow with n (a few PCR
+    stages), checked at 1e-12."""
+    torch, ridc = env
+    n, nt, r, T = 1 << 28, 2, 0.5, 0.02
+    L = 2 * math.pi
+    h, dt = L / n, T / nt
+    prob = dict(dim=1, bc="periodic", n=n, length=L, fe="none", a=0.0, nu=r * h * h / dt, T=T,
+                nt=nt, order=1)
+    _say(f"case: 1D sine mode n=2^28 nt={nt} order 1 r={r}")
+    i8 = torch.arange(n, dtype=torch.int64, device="cuda") % 8
+    x0 = torch.sin((math.pi / 4) * i8.to(torch.float64))
+    del i8
+    uT = torch.empty_like(x0)
+    s = ridc.Ridc(prob, dt=dt)
+    s.integrate(x0, nt, uT)
+    s.close()
+    amp = (1.0 + 4.0 * r * math.sin(math.pi / 8) ** 2) ** (-nt)
+    rng = np.random.default_rng(1 << 28)
+    idx = np.concatenate([rng.integers(0, n, 4000), [0, 1, n // 2, n - 2, n - 1]])
+    got = uT[torch.tensor(idx, dtype=torch.int64, device="cuda")].cpu().numpy()
+    del x0, uT
+    want = amp * np.sin((math.pi / 4) * (idx % 8))
+    err = float(np.max(np.abs(got - want)))
+    _say(f"  amplitude {amp:.6f}, max abs error {err:.3e}")
+    assert err <= 1e-12
+
+
 def test_batch_bitwise_equals_solo(env):
     torch, ridc = env
     cases = workloads.config_batched_1d(count=12, nt=120, T=0.03)
