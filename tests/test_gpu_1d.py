@@ -349,7 +349,8 @@ def test_tilings_are_bitwise_identical(env):
 @pytest.mark.parametrize("bc,n,order,nt", [("periodic", 1000, 4, 50), ("dirichlet", 999, 4, 40),
                                            ("periodic", 2048, 4, 30), ("dirichlet", 3000, 3, 30),
                                            ("periodic", 128, 1, 20), ("dirichlet", 64, 6, 25),
-                                           ("periodic", 4096, 2, 40)])
+                                           ("periodic", 4096, 2, 40), ("periodic", 128, 4, 60),
+                                           ("dirichlet", 200, 4, 30)])
 def test_fused_integration_equals_per_step_kernel(env, bc, n, order, nt):
     """Systems that fit one CU run their whole integration in one workgroup; the result is
     bitwise that of one launch per pipeline step."""
