@@ -1,13 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the RIDC hot path on one MI355X.
 
-Default workload (``--workload reacdiff1d``): 1D reaction-diffusion u_t = nu u_xx + u(1-u),
-Dirichlet 0 on [0,1], N = 8192 interior points, nu = 1e-3, eight seeded Gaussian bumps, RIDC
-order 4 (predictor + 3 correctors), T = 1, Nt = 2000 uniform steps, FP64.  One bench step is
-one whole integration (all Nt time steps of all four levels, Nt + 6 pipeline steps) with the
-data already resident in HBM.  Other workloads: ``advdiff1d`` (N=128 periodic
-advection-diffusion), ``reacdiff2d`` (1024^2, Nt=500, ``--prec fp64|fp32|bf16x3``) and
-``batched1d`` (256 ragged periodic instances, Nt=1000, T=0.25, one grouped launch per step).
+Default workload (``--workload reacdiff2d``): 2D reaction-diffusion u_t = nu Lap u + u(1-u),
+Dirichlet 0 on [0,1]^2, 1024 x 1024 interior points, nu = 1e-4, eight seeded radial Gaussian
+bumps, RIDC order 4 (predictor + 3 correctors), T = 1, Nt = 500.  One bench step is one whole
+integration (all Nt time steps of all four levels, Nt + 6 pipeline steps) with the data already
+resident in HBM.  ``value`` is the FP64 rate; the ``matched`` block times the same integration
+with split-BF16 (and FP32) transforms plus one FP64 refinement and states its relative L2
+distance to the FP64 result against the RIDC4 discretisation error (Richardson with an FP64 run
+at 2 Nt): a reduced-precision run is matched when that distance is at most 0.1 of it.
+
+Other workloads: ``reacdiff1d`` (N = 8192 Dirichlet, Nt = 2000), ``advdiff1d`` (N = 128
+periodic), ``batched1d`` (256 ragged periodic instances, Nt = 1000, T = 0.25, one grouped launch
+per step), ``serving`` (Poisson 2D request stream) and the paper's own 1D cases.
 
 Prints one JSON line: grid-point-steps/s (unknowns x Nt / wall time), the roofline of the
 dominant kernel (HIP events around back-to-back launches on the library's stream), and the FP64
@@ -83,16 +88,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="reacdiff1d",
+    ap.add_argument("--workload", default="reacdiff2d",
                     choices=["reacdiff1d", "advdiff1d", "reacdiff2d", "batched1d", "serving",
                              "paper_advdiff", "paper_burgers"])
     ap.add_argument("--rate", type=float, default=200.0,
                     help="serving: Poisson arrival rate in requests/s (the configured load is 200)")
-    ap.add_argument("--horizon", type=float, default=10.0,
+    ap.add_argument("--horizon", type=float, default=60.0,
                     help="serving: seconds of Poisson arrivals admitted")
-    ap.add_argument("--max-wall", type=float, default=40.0,
+    ap.add_argument("--max-wall", type=float, default=90.0,
                     help="serving: wall-clock cap; work still queued then is reported unserved")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+                    help="2D: transform precision of the value line (the matched block always "
+                         "times the reduced-precision transforms)")
+    ap.add_argument("--no-matched", action="store_true",
+                    help="2D: skip the reduced-precision (matched) integrations")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true",
                     help="2D: skip the FP64 reference integrations (error checks), e.g. when "
@@ -115,20 +124,23 @@ CPU_SAMPLE_S = 10.0      # seconds of oracle work timed for the CPU baseline
 
 
 def oracle_time(fn, min_s=CPU_SAMPLE_S):
-    """Run fn() with BLAS/FFT threads limited to one, again and again until min_s seconds have
-    passed (at least once); returns (first result, repetitions, seconds)."""
+    """Run fn() on one core -- BLAS threads limited to one and scipy.fft's workers set to one
+    (the oracle's transforms follow scipy.fft.set_workers) -- again and again until min_s
+    seconds have passed (at least once); returns (first result, repetitions, seconds)."""
+    import scipy.fft
     try:
         from threadpoolctl import threadpool_limits
         limiter = threadpool_limits(limits=1)
     except Exception:  # noqa: BLE001
         limiter = None
-    t = time.perf_counter()
-    out = fn()
-    reps = 1
-    while time.perf_counter() - t < min_s:
-        fn()
-        reps += 1
-    dt = time.perf_counter() - t
+    with scipy.fft.set_workers(1):
+        t = time.perf_counter()
+        out = fn()
+        reps = 1
+        while time.perf_counter() - t < min_s:
+            fn()
+            reps += 1
+        dt = time.perf_counter() - t
     if limiter is not None:
         limiter.unregister()
     return out, reps, dt
@@ -181,22 +193,31 @@ def roofline_single(ridc, s, x0, nt, reps, bound, prec):
                 "kernel_frac": round(work / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
                 "note": "achieved counts the method's stored-window bytes per unknown-step; the "
                         "kernel recomputes f and moves kernel_bytes_per_launch"}
+    return roofline_pass(us, work, s.side, prec)
+
+
+def roofline_pass(us, dense, n, prec):
+    """Roofline of one transform pass over every level: `dense` is the plain product's 2 n^3
+    flops per level.  The pass folds the symmetric sine matrix by its reflection symmetry when n
+    is a multiple of 64, so its contraction has half that length: n^3 flops per level are the
+    work of the folded product, which is what the matrix cores must issue (three BF16 products
+    per folded product in the split-BF16 pass).  achieved/frac count that issued work against
+    the dtype's dense MFMA peak; the dense count is kept as a labelled extra."""
+    fold = 0.5 if n % 64 == 0 else 1.0
+    products = 3.0 if prec == "bf16x3" else 1.0
+    issued = dense * fold * products
     peak = MFMA_PEAK_TFLOPS[prec]
-    ach = work / (us * 1e-6) / 1e12
-    # the pass folds the sine matrix by its reflection symmetry when n is a multiple of 64, so
-    # the matrix cores issue half the algorithmic products (three BF16 products per split one)
-    n = s.side
-    issued = work * (0.5 if n % 64 == 0 else 1.0) * (3.0 if prec == "bf16x3" else 1.0)
-    issued_peak = MFMA_PEAK_TFLOPS["bf16x3"] if prec == "bf16x3" else peak
+    ach = issued / (us * 1e-6) / 1e12
     return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(ach / peak, 5), "traffic": None,
-            "kernel": f"k_pass2d<{prec}>", "launch_us": round(us, 3), "flops_per_launch": work,
-            "issued_mfma_tflops": round(issued / (us * 1e-6) / 1e12, 3),
-            "issued_frac": round(issued / (us * 1e-6) / 1e12 / issued_peak, 5),
-            "note": "achieved counts the algorithmic 2n^3 flops per level and pass; the kernel "
-                    "folds the symmetric sine matrix (n % 64 == 0) and issues half of them"
-                    + ("; the split-BF16 pass issues 3 BF16 products per folded product"
-                       if prec == "bf16x3" else "")}
+            "kernel": f"k_pass2d<{prec}>", "launch_us": round(us, 3),
+            "flops_per_launch": issued,
+            "dense_flops_per_launch": dense,
+            "dense_equivalent_tflops": round(dense / (us * 1e-6) / 1e12, 3),
+            "note": ("flops_per_launch is the folded contraction's n^3 per level"
+                     + (" times 3 BF16 products" if prec == "bf16x3" else "")
+                     + "; dense_flops_per_launch is the plain product's 2 n^3 per level, which "
+                       "the folded kernel does not issue")}
 
 
 def bench_1d(args, torch, ridc, which):
@@ -258,6 +279,25 @@ def bench_1d(args, torch, ridc, which):
                 roofline=roof, cpu=cpu, check={"rel_l2_vs_oracle": rel})
 
 
+def stencil_roofline(ridc, s, x0, nt, reps):
+    """HBM roofline of the right-hand-side kernel (stencils and quadrature of every level) at a
+    steady-state step of the same integration."""
+    P, n = s.order, s.side
+    s.begin(x0, nt)
+    ridc.advance([s], P * (P - 1) // 2)
+    us, kbytes = s.stencil_time(reps)
+    s.sync()
+    alg = method_step_bytes(P, n * n)
+    ach = alg / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "k_rhs2d", "launch_us": round(us, 3), "bytes_per_launch": alg,
+            "kernel_bytes_per_launch": kbytes,
+            "kernel_frac": round(kbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
+            "note": "achieved counts the method's stored-window bytes per unknown-step; the "
+                    "kernel recomputes f and moves kernel_bytes_per_launch"}
+
+
 def bench_2d(args, torch, ridc):
     import workloads
     prob, u0 = workloads.config_reacdiff_2d()
@@ -265,22 +305,10 @@ def bench_2d(args, torch, ridc):
         prob = dict(prob, nt=args.nt, T=prob["T"] * args.nt / prob["nt"])
     n, nt, P = prob["n"], prob["nt"], prob["order"]
     steps, warmup = args.steps or 3, args.warmup if args.warmup is not None else 1
+    reps = max(10, args.reps // 10)
     el, out, s, x0, _ = run_single(args, torch, ridc, prob, u0, args.prec, steps, warmup)
-    roof = roofline_single(ridc, s, x0, nt, max(10, args.reps // 10), "mfma", args.prec)
-    # the stencil/quadrature kernel of the same step is HBM-bound: its own roofline
-    s.begin(x0, nt)
-    ridc.advance([s], P * (P - 1) // 2)
-    us_rhs, bytes_rhs = s.stencil_time(max(10, args.reps // 10))
-    s.sync()
-    alg_rhs = method_step_bytes(P, n * n)
-    ach_rhs = alg_rhs / (us_rhs * 1e-6) / 1e9
-    roof_rhs = {"bound": "hbm", "achieved": round(ach_rhs, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach_rhs / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": "k_rhs2d", "launch_us": round(us_rhs, 3), "bytes_per_launch": alg_rhs,
-                "kernel_bytes_per_launch": bytes_rhs,
-                "kernel_frac": round(bytes_rhs / (us_rhs * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
-                "note": "achieved counts the method's stored-window bytes per unknown-step; the "
-                        "kernel recomputes f and moves kernel_bytes_per_launch"}
+    roof = roofline_single(ridc, s, x0, nt, reps, "mfma", args.prec)
+    roof_rhs = stencil_roofline(ridc, s, x0, nt, reps)
     if args.nt is None:
         roof["traffic"] = measured_traffic("reacdiff2d", args.prec)
         roof_rhs["traffic"] = measured_traffic("reacdiff2d_rhs", args.prec)
@@ -296,46 +324,63 @@ def bench_2d(args, torch, ridc):
         check["rel_l2_vs_oracle_subgrid"] = float(
             np.linalg.norm(out.reshape(n, n)[::8, ::8] - ref["top_sub8"])
             / np.linalg.norm(ref["top_sub8"]))
-    if args.no_check:
-        return finish_2d(args, prob, u0, n, nt, P, el, steps, warmup, roof, roof_rhs, check)
-    # discretisation error of RIDC4 at this Nt (Richardson with an FP64 run at 2 Nt)
-    prob2 = dict(prob, nt=2 * nt)
-    s2 = ridc.Ridc(prob2, prec="fp64")
-    u2 = s2.integrate(x0, 2 * nt).cpu().numpy()
-    s2.close()
-    err_disc = 16.0 / 15.0 * float(np.linalg.norm(out - u2) / np.linalg.norm(u2)) \
-        if args.prec == "fp64" else None
-    if args.prec != "fp64":
-        s3 = ridc.Ridc(prob, prec="fp64")
-        u64 = s3.integrate(x0, nt).cpu().numpy()
-        s3.close()
+    matched = {}
+    if not args.no_check:
+        # discretisation error of RIDC4 at this Nt: Richardson with an FP64 run at 2 Nt
+        s2 = ridc.Ridc(dict(prob, nt=2 * nt), prec="fp64")
+        u2 = s2.integrate(x0, 2 * nt).cpu().numpy()
+        s2.close()
+        u64 = out
+        if args.prec != "fp64":
+            s3 = ridc.Ridc(prob, prec="fp64")
+            u64 = s3.integrate(x0, nt).cpu().numpy()
+            s3.close()
+            check["rel_l2_vs_fp64_gpu"] = float(np.linalg.norm(out - u64) / np.linalg.norm(u64))
         err_disc = 16.0 / 15.0 * float(np.linalg.norm(u64 - u2) / np.linalg.norm(u2))
-        mixed = float(np.linalg.norm(out - u64) / np.linalg.norm(u64))
-        check["rel_l2_vs_fp64_gpu"] = mixed
-        check["matched"] = bool(mixed <= 0.1 * err_disc)
-    check["err_disc_ridc4"] = err_disc
-    return finish_2d(args, prob, u0, n, nt, P, el, steps, warmup, roof, roof_rhs, check)
-
-
-def finish_2d(args, prob, u0, n, nt, P, el, steps, warmup, roof, roof_rhs, check):
+        check["err_disc_ridc4"] = err_disc
+        if args.prec != "fp64":
+            check["matched"] = bool(check["rel_l2_vs_fp64_gpu"] <= 0.1 * err_disc)
+        if not args.no_matched and args.prec == "fp64":
+            for prec in ("bf16x3", "fp32"):
+                el_m, out_m, sm, _, _ = run_single(args, torch, ridc, prob, u0, prec, steps,
+                                                   warmup)
+                roof_m = roofline_single(ridc, sm, x0, nt, reps, "mfma", prec)
+                sm.close()
+                dist = float(np.linalg.norm(out_m - u64) / np.linalg.norm(u64))
+                matched[prec] = {
+                    "value": round(n * n * nt / el_m, 1), "unit": "grid-point-steps/s",
+                    "ms_per_step": round(1e3 * el_m, 4), "speedup_vs_fp64": round(el / el_m, 4),
+                    "transforms": {"bf16x3": "split-BF16 (hi/lo, 3 products, FP32 accumulation)",
+                                   "fp32": "FP32"}[prec] + " + one FP64 residual refinement; "
+                                                          "FP64 sums and level differences",
+                    "rel_l2_vs_fp64": dist, "err_disc": err_disc,
+                    "matched": bool(dist <= 0.1 * err_disc),
+                    "roofline": {k: roof_m[k] for k in ("bound", "achieved", "peak", "unit",
+                                                        "frac", "kernel", "launch_us",
+                                                        "flops_per_launch")}}
     cpu = None
     if not args.no_cpu:
         from oracle import Problem, ridc_pipelined
         nts = 6
-        _, reps, sec = oracle_time(lambda: ridc_pipelined(Problem.from_dict(prob), u0, nts, P))
-        cpu = {"value": round(n * n * nts * reps / sec, 1), "unit": "grid-point-steps/s",
+        _, creps, sec = oracle_time(lambda: ridc_pipelined(Problem.from_dict(prob), u0, nts, P))
+        cpu = {"value": round(n * n * nts * creps / sec, 1), "unit": "grid-point-steps/s",
                "cores": 1, "kind": "oracle",
                "sample": f"the full {n}^2 grid for the first {nts} time steps of all {P} levels, "
-                         f"{reps}x ({P * nts * reps} level steps, {sec:.1f} s), one thread"}
+                         f"{creps}x ({P * nts * creps} level steps, {sec:.1f} s) on one core "
+                         f"(one BLAS thread, one FFT worker); host has {os.cpu_count()} logical "
+                         "CPUs"}
     desc = ("2D reaction-diffusion u_t = nu Lap u + u(1-u), Dirichlet [0,1]^2, 1024x1024, "
             f"nu=1e-4, 8 seeded bumps, RIDC order 4, T={prob['T']:g}, Nt={nt}, "
             f"transforms {args.prec}")
-    return dict(value=n * n * nt / el, ms=1e3 * el, steps=steps, warmup=warmup,
+    line = dict(value=n * n * nt / el, ms=1e3 * el, steps=steps, warmup=warmup,
                 dtype={"fp64": "f64", "fp32": "f32 transforms, f64 sums",
                        "bf16x3": "bf16x3 transforms, f64 sums"}[args.prec],
                 config={"workload": desc, "n": n, "nt": nt, "order": P, "prec": args.prec,
                         "pipeline_steps": nt + P * (P - 1) // 2},
                 roofline=roof, roofline_stencil=roof_rhs, cpu=cpu, check=check)
+    if matched:
+        line["matched"] = matched
+    return line
 
 
 def bench_batched(args, torch, ridc):
@@ -512,6 +557,8 @@ def run_workload(args, torch, ridc):
     }
     if r.get("roofline_stencil"):
         line["roofline_stencil"] = r["roofline_stencil"]
+    if r.get("matched"):
+        line["matched"] = r["matched"]
     return line
 
 

@@ -281,6 +281,37 @@ void plan_layout(const ridc_problem* p, const Tile1D* tile, Layout* L) {
   L->total = L->rings + L->weights + L->flag + L->items + L->blocks + L->ws2d;
 }
 
+// Kernel-argument descriptor of a single instance's level step (k_step1d_solo): level rings and
+// their slot counts, per-level weight tables (W[0] unused), the device PCR tables, the tiling.
+void fill_solo(const ridc_problem& p, double h, const PcrPlan& pcr, const Tile1D& tile,
+               double* const* ring, const int* R, const double* const* W, const double* gamma,
+               const int32_t* shift, int64_t nt, Solo1D* out) {
+  Solo1D a{};
+  for (int j = 0; j < p.order; ++j) {
+    a.ring[j] = ring[j];
+    a.W[j] = j > 0 ? W[j] : nullptr;
+    a.R[j] = R[j];
+  }
+  a.gamma = gamma;
+  a.shift = shift;
+  a.nt = nt;
+  a.nchunks = tile.wrap ? 1 : (int)((p.n + tile.B - 1) / tile.B);
+  a.n = (int32_t)p.n;
+  a.M = (int32_t)(p.bc == RIDC_BC_PERIODIC ? p.n : 2 * p.n + 2);
+  a.bc = p.bc;
+  a.fe = p.fe_kind;
+  a.stages = pcr.stages;
+  a.wrap = tile.wrap;
+  a.B = tile.wrap ? 0 : tile.B;
+  a.H = tile.wrap ? 0 : (int)halo_rows(pcr);
+  a.nt_store = tile.nt_store;
+  a.dt = p.dt;
+  a.ce = explicit_coeff(p.fe_kind, p.a, h);
+  a.nu_h2 = p.nu / (h * h);
+  a.inv_divisor = 1.0 / pcr.divisor;
+  *out = a;
+}
+
 void build_items_1d(ridc_handle* h, const Tile1D& tile) {
   const ridc_problem& p = h->p;
   const int P = h->P;
@@ -324,36 +355,20 @@ void build_items_1d(ridc_handle* h, const Tile1D& tile) {
   h->lds = lds;
   h->threads = tile.threads;
   (void)prepare_1d_step(h->threads, P, h->lds);
-  Solo1D& a = h->solo;
-  a = Solo1D{};
-  for (int j = 0; j < P; ++j) {
-    a.ring[j] = h->ring[j];
-    a.W[j] = j > 0 ? h->W + h->woff[j] : nullptr;
-    a.R[j] = h->R[j];
-  }
-  a.gamma = (const double*)((const char*)h->d_items + offsetof(Lvl1D, gamma));
-  a.shift = (const int32_t*)((const char*)h->d_items + offsetof(Lvl1D, shift));
-  a.nt = h->nt < 0 ? 0 : h->nt;
-  a.nchunks = nchunks;
-  a.n = (int32_t)p.n;
-  a.M = (int32_t)M;
-  a.bc = p.bc;
-  a.fe = p.fe_kind;
-  a.stages = h->pcr.stages;
-  a.wrap = tile.wrap;
-  a.B = tile.wrap ? 0 : tile.B;
-  a.H = H;
-  a.nt_store = tile.nt_store;
-  a.dt = p.dt;
-  a.ce = explicit_coeff(p.fe_kind, p.a, h->h);
-  a.nu_h2 = p.nu / (h->h * h->h);
-  a.inv_divisor = 1.0 / h->pcr.divisor;
+  std::vector<const double*> W(P, nullptr);
+  for (int j = 1; j < P; ++j) W[j] = h->W + h->woff[j];
+  fill_solo(p, h->h, h->pcr, tile, h->ring.data(), h->R.data(), W.data(),
+            (const double*)((const char*)h->d_items + offsetof(Lvl1D, gamma)),
+            (const int32_t*)((const char*)h->d_items + offsetof(Lvl1D, shift)),
+            h->nt < 0 ? 0 : h->nt, &h->solo);
   h->solo_blocks = P * nchunks;
 }
 
 // Grouped launch tables for ridc_advance over several 1D handles (one set per thread and
-// device; uploads are ordered on the stream, the pinned staging copy is reused only after the
-// previous upload completed).
+// device).  Two events guard their reuse: `done` follows the upload of the pinned staging copy
+// (the host waits for it before rewriting the staging), and `used` follows the last launch that
+// read the device tables (an upload on another stream waits for it on the device, so that the
+// tables are never rewritten under a kernel still reading them).
 struct BatchArena {
   int device = -1;
   Lvl1D* d_items = nullptr;
@@ -369,13 +384,33 @@ struct BatchArena {
   size_t cap_copy = 0;
   hipEvent_t done = nullptr;
   bool pending = false;
+  hipEvent_t used = nullptr;
+  hipStream_t used_stream = nullptr;
+  bool in_use = false;
 };
 
 thread_local BatchArena g_arena;
 
+// Mark the tables as read by work enqueued on `stream` so far (call after the launches).
+int arena_release(hipStream_t stream) {
+  RIDC_HIP_TRY(hipEventRecord(g_arena.used, stream));
+  g_arena.used_stream = stream;
+  g_arena.in_use = true;
+  return RIDC_OK;
+}
+
+// Before a table is freed for a larger one: every launch reading it has finished.
+int arena_drain() {
+  if (g_arena.in_use) RIDC_HIP_TRY(hipEventSynchronize(g_arena.used));
+  g_arena.in_use = false;
+  return RIDC_OK;
+}
+
 int arena_reserve_fused(size_t n) {
-  // called after arena_reserve (device, event and pending upload handled there)
+  // called after arena_reserve (device, events and pending upload handled there)
   if (n > g_arena.cap_fused) {
+    int rc = arena_drain();
+    if (rc != RIDC_OK) return rc;
     if (g_arena.d_fused) (void)hipFree(g_arena.d_fused);
     if (g_arena.h_fused) (void)hipHostFree(g_arena.h_fused);
     g_arena.d_fused = nullptr;
@@ -390,7 +425,8 @@ int arena_reserve_fused(size_t n) {
   return RIDC_OK;
 }
 
-int arena_reserve(size_t nitems, size_t nblocks) {
+// Make the tables (at least nitems items and nblocks blocks) ready for an upload on `stream`.
+int arena_reserve(size_t nitems, size_t nblocks, hipStream_t stream) {
   int dev = 0;
   RIDC_HIP_TRY(hipGetDevice(&dev));
   if (g_arena.device != dev) {
@@ -398,10 +434,16 @@ int arena_reserve(size_t nitems, size_t nblocks) {
     g_arena.device = dev;
   }
   if (!g_arena.done) RIDC_HIP_TRY(hipEventCreateWithFlags(&g_arena.done, hipEventDisableTiming));
+  if (!g_arena.used) RIDC_HIP_TRY(hipEventCreateWithFlags(&g_arena.used, hipEventDisableTiming));
   if (g_arena.pending) {
     RIDC_HIP_TRY(hipEventSynchronize(g_arena.done));
     g_arena.pending = false;
   }
+  // launches of another stream may still read the tables this upload overwrites
+  if (g_arena.in_use && g_arena.used_stream != stream)
+    RIDC_HIP_TRY(hipStreamWaitEvent(stream, g_arena.used, 0));
+  if ((nitems > g_arena.cap_items || nblocks > g_arena.cap_blocks) && arena_drain() != RIDC_OK)
+    return RIDC_E_HIP;
   if (nitems > g_arena.cap_items) {
     if (g_arena.d_items) (void)hipFree(g_arena.d_items);
     if (g_arena.h_items) (void)hipHostFree(g_arena.h_items);
@@ -597,7 +639,7 @@ int stage_batch_1d(const std::vector<ridc_handle*>& hs, const BatchTile& bt, boo
     nitems += hs[i]->P;
     nblocks += (size_t)(nch * hs[i]->P);
   }
-  int rc = arena_reserve(nitems, nblocks);
+  int rc = arena_reserve(nitems, nblocks, stream);
   if (rc != RIDC_OK) return rc;
   std::vector<std::pair<int64_t, Blk1D>> order;
   order.reserve(nblocks);
@@ -660,9 +702,11 @@ int arm_handle(ridc_handle* h, const double* u0_dev, int64_t nsteps) {
 // the batch arena's pinned staging; one launch per 65535 items (the grid's y extent).
 int stage_copies(const std::vector<CopyItem>& c, hipStream_t stream) {
   if (c.empty()) return RIDC_OK;
-  int rc = arena_reserve(0, 0);
+  int rc = arena_reserve(0, 0, stream);
   if (rc != RIDC_OK) return rc;
   if (c.size() > g_arena.cap_copy) {
+    rc = arena_drain();
+    if (rc != RIDC_OK) return rc;
     if (g_arena.d_copy) (void)hipFree(g_arena.d_copy);
     if (g_arena.h_copy) (void)hipHostFree(g_arena.h_copy);
     g_arena.d_copy = nullptr;
@@ -687,7 +731,7 @@ int stage_copies(const std::vector<CopyItem>& c, hipStream_t stream) {
     const int cnt = (int)std::min<size_t>(65535, c.size() - off);
     RIDC_HIP_TRY(launch_copy_items(g_arena.d_copy + off, cnt, most, stream));
   }
-  return RIDC_OK;
+  return arena_release(stream);
 }
 
 }  // namespace
@@ -907,7 +951,7 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
     for (auto* h : h1) (h->fused ? hf : hs).push_back(h);
     h1.swap(hs);
     if (!hf.empty()) {
-      rc = arena_reserve(1, 1);
+      rc = arena_reserve(1, 1, stream);
       if (rc != RIDC_OK) return rc;
       rc = arena_reserve_fused(hf.size());
       if (rc != RIDC_OK) return rc;
@@ -932,6 +976,8 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
       g_arena.pending = true;
       RIDC_HIP_TRY(launch_fused_1d(g_arena.d_fused, nullptr, (int)hf.size(), maxP, 512, lds,
                                    stream));
+      rc = arena_release(stream);
+      if (rc != RIDC_OK) return rc;
       for (auto* h : hf) h->sigma = std::min(h->total, h->sigma + max_steps);
     }
   }
@@ -949,6 +995,8 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
     for (int64_t s = 1; s <= steps1; ++s)
       RIDC_HIP_TRY(launch_1d_step(g_arena.d_items, g_arena.d_blocks, st.nblocks, st.threads,
                                   st.maxP, st.lds, s, stream));
+    rc = arena_release(stream);
+    if (rc != RIDC_OK) return rc;
     for (auto* h : h1) h->sigma += std::min(max_steps, h->total - h->sigma);
   }
   // ---- 2D handles: grouped per step by the 2D planner -----------------------------------------
@@ -1207,6 +1255,7 @@ int ridc_autotune_batch(ridc_handle* const* hs, int32_t count, int32_t* threads_
                              st.lds, s, stream) != hipSuccess)
             rc = fail(RIDC_E_HIP, "batch tuning launch failed");
         (void)hipEventRecord(b, stream);
+        if (rc == RIDC_OK) rc = arena_release(stream);
         if (rc != RIDC_OK) break;
         float ms = 0;
         if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
@@ -1274,6 +1323,7 @@ int ridc_batch_kernel_time(ridc_handle* const* hs, int32_t count, int32_t reps,
                        st.lds, 1, stream) != hipSuccess)
       rc = fail(RIDC_E_HIP, "grouped launch failed");
   (void)hipEventRecord(b, stream);
+  if (rc == RIDC_OK) rc = arena_release(stream);
   float ms = 0;
   if (rc == RIDC_OK &&
       (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))

@@ -1159,8 +1159,10 @@ void run_stages(int prec, const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nma
   }
 }
 
-// Launch tables of grouped plans (one set per calling thread and device; the pinned staging
-// copy is reused only after its previous upload completed).
+// Launch tables of grouped plans (one set per calling thread and device).  `done` follows the
+// upload of the pinned staging copy (the host waits for it before rewriting the staging);
+// `used` follows the last launch that read the device tables, and an upload on another stream
+// waits for it on the device, so the tables are never rewritten under a running kernel.
 struct Arena2D {
   int device = -1;
   Lvl2D* d_lv = nullptr;
@@ -1170,10 +1172,13 @@ struct Arena2D {
   size_t cap_lv = 0, cap_ps = 0;
   hipEvent_t done = nullptr;
   bool pending = false;
+  hipEvent_t used = nullptr;
+  hipStream_t used_stream = nullptr;
+  bool in_use = false;
 };
 thread_local Arena2D g_a2;
 
-int arena2d_reserve(size_t nlv, size_t nps) {
+int arena2d_reserve(size_t nlv, size_t nps, hipStream_t stream) {
   int dev = 0;
   RIDC_HIP_TRY(hipGetDevice(&dev));
   if (g_a2.device != dev) {
@@ -1181,9 +1186,16 @@ int arena2d_reserve(size_t nlv, size_t nps) {
     g_a2.device = dev;
   }
   if (!g_a2.done) RIDC_HIP_TRY(hipEventCreateWithFlags(&g_a2.done, hipEventDisableTiming));
+  if (!g_a2.used) RIDC_HIP_TRY(hipEventCreateWithFlags(&g_a2.used, hipEventDisableTiming));
   if (g_a2.pending) {
     RIDC_HIP_TRY(hipEventSynchronize(g_a2.done));
     g_a2.pending = false;
+  }
+  if (g_a2.in_use && g_a2.used_stream != stream)
+    RIDC_HIP_TRY(hipStreamWaitEvent(stream, g_a2.used, 0));
+  if (g_a2.in_use && (nlv > g_a2.cap_lv || nps > g_a2.cap_ps)) {
+    RIDC_HIP_TRY(hipEventSynchronize(g_a2.used));   // a table is about to be freed
+    g_a2.in_use = false;
   }
   if (nlv > g_a2.cap_lv) {
     if (g_a2.d_lv) (void)hipFree(g_a2.d_lv);
@@ -1240,7 +1252,7 @@ int plan2d_advance(Plan2D* const* pls, int count, const int64_t* sigma_before, i
     nlv += pls[i]->P;
     nps += (size_t)pls[i]->P * pls[i]->npass;
   }
-  int rc = arena2d_reserve(nlv, nps);
+  int rc = arena2d_reserve(nlv, nps, stream);
   if (rc != RIDC_OK) return rc;
   struct G {
     int prec, cnt;
@@ -1282,6 +1294,9 @@ int plan2d_advance(Plan2D* const* pls, int count, const int64_t* sigma_before, i
     for (auto& g : gs)
       run_stages(g.prec, g_a2.d_lv + g.lv_off, g_a2.d_ps + g.ps_off, g.cnt, g.n, s, stream);
   RIDC_HIP_TRY(hipGetLastError());
+  RIDC_HIP_TRY(hipEventRecord(g_a2.used, stream));
+  g_a2.used_stream = stream;
+  g_a2.in_use = true;
   return RIDC_OK;
 }
 

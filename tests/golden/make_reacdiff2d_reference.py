@@ -14,6 +14,7 @@ import sys
 import time
 
 import numpy as np
+import scipy.fft
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
@@ -33,7 +34,8 @@ def main(path):
         if j == 0 and m % 25 == 0:
             print(f"oracle step {sigma} (level 0 at t_{m}), {time.time() - t0:.0f} s", flush=True)
 
-    levels = ridc_pipelined(p, u0, nt, order, trace=trace)
+    with scipy.fft.set_workers(os.cpu_count() or 1):     # the values do not depend on it
+        levels = ridc_pipelined(p, u0, nt, order, trace=trace)
     rng = np.random.default_rng(20240)
     idx = rng.choice(n * n, size=4096, replace=False)
     np.savez_compressed(

@@ -45,3 +45,23 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+@pytest.mark.parametrize("prec,products", [("fp64", 1), ("fp32", 1), ("bf16x3", 3)])
+def test_pass_roofline_counts_the_folded_issued_work(bench, prec, products):
+    """A folded pass (n a multiple of 64) issues n^3 flops per level (three BF16 products per
+    folded one in the split-BF16 pass): the frac is that work over the dtype's peak, so a pass
+    running exactly at peak reads 1.0, and the plain 2 n^3 count is a labelled extra."""
+    n, levels = 1024, 4
+    dense = 2.0 * n**3 * levels
+    issued = n**3 * levels * products
+    peak = bench.MFMA_PEAK_TFLOPS[prec]
+    us_at_peak = issued / (peak * 1e12) * 1e6
+    r = bench.roofline_pass(us_at_peak, dense, n, prec)
+    assert r["flops_per_launch"] == issued and r["dense_flops_per_launch"] == dense
+    assert abs(r["frac"] - 1.0) < 1e-4
+    r = bench.roofline_pass(2 * us_at_peak, dense, n, prec)
+    assert abs(r["frac"] - 0.5) < 1e-4 and r["peak"] == peak
+    # an unfolded side (n % 64 != 0) issues the plain product
+    r = bench.roofline_pass(1.0, 2.0 * 96**3, 96, prec)
+    assert r["flops_per_launch"] == 2.0 * 96**3 * products

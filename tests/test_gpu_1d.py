@@ -1,8 +1,8 @@
 """GPU parity of the 1D RIDC path (fused level-step + PCR in LDS) against the FP64 oracle.
 
-Bar: relative L2 <= 1e-12 per level against the oracle on the same seeded inputs (both FP64; the
-GPU contracts to FMA and solves by PCR, the oracle solves by FFT or banded LU, so only rounding
-differs).  Tiling, batching, graph replay and repetition must not change a single bit.
+Bar: relative L2 <= 1e-12 per level against the oracle on the same seeded inputs, and the largest
+pointwise difference <= 1e-12 of the largest value (both FP64; the GPU contracts to FMA and solves
+by PCR, the oracle solves by FFT or banded LU, so only rounding differs).  Tiling, batching, graph replay and repetition must not change a single bit.
 """
 import math
 import sys
@@ -56,8 +56,10 @@ def check_against_oracle(env, prob, u0, nt=None, tol=TOL):
     ref = ridc_pipelined(p, np.asarray(u0), nt, prob["order"])
     top, lvs = run_gpu(env, prob, u0, nt)
     for j in range(prob["order"]):
-        err = rel_l2(lvs[j], ref[j]) if np.linalg.norm(ref[j]) > 0 else np.abs(lvs[j]).max()
-        assert err <= tol, (j, err)
+        scale = np.abs(ref[j]).max()
+        err = rel_l2(lvs[j], ref[j]) if scale > 0 else np.abs(lvs[j]).max()
+        emax = np.abs(lvs[j] - ref[j]).max() / (scale if scale > 0 else 1.0)
+        assert err <= tol and emax <= tol, (j, err, emax)
     np.testing.assert_array_equal(top, lvs[-1])
     return ref, top
 

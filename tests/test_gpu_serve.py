@@ -1,6 +1,7 @@
 """Serving on the GPU: requests of mixed sizes, orders, dimensions and precisions admitted while
 others run produce, bit for bit, the result of the same request integrated alone, and the
 reduced-precision ones stay within their tolerance of the FP64 oracle."""
+import os
 import sys
 
 import numpy as np
@@ -10,6 +11,9 @@ import workloads
 from oracle import Problem, rel_l2, ridc_pipelined
 
 pytestmark = pytest.mark.gpu
+
+# FP64: the spec bar.  Reduced precision: see test_gpu_2d.TOL (measured errors x 100).
+SERVE_TOL = {"fp64": 1e-12, "fp32": 1e-11, "bf16x3": 1e-8}
 
 
 def _mix():
@@ -63,3 +67,48 @@ def test_served_results_equal_solo_results():
                 r.prob["n"], r.prob["n"]), r.nsteps, r.prob["order"])[-1]
             err = rel_l2(r.result.cpu().numpy().reshape(ref.shape), ref)
             assert err < (1e-11 if r.prec == "fp32" else 1e-8), err
+
+
+SERVING_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "serving_first_per_side.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(SERVING_GOLDEN), reason="serving samples not generated")
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "fp32"])
+def test_served_requests_of_every_side_against_oracle(prec):
+    """The first request of each side (128, 256, 512, 1024) of the 200 req/s serving stream,
+    served together through the continuous-batching server, against the FP64 oracle's values
+    stored in tests/golden (every point of the sampled set, the norm, the sum and the
+    every-8th-point sub-grid)."""
+    import torch
+    from paper_1209_4297_amd.serve import GpuExecutor, Request, Server
+
+    ref = np.load(SERVING_GOLDEN)
+    stream = workloads.serving_requests(rate=200.0, duration=60.0)
+    reqs = []
+    for n in (128, 256, 512, 1024):
+        i = int(ref[f"n{n}_request"])
+        a = stream[i]
+        assert a["prob"]["n"] == n
+        u0 = workloads.bumps_2d(n, a["bump_seed"]).reshape(-1)
+        reqs.append(Request(rid=i, prob=a["prob"], u0=u0, nsteps=a["prob"]["nt"], prec=prec))
+    srv = Server(GpuExecutor(), hbm_budget=8 * 2**30, max_slots=8, tick_steps=16)
+    for r in reqs:
+        srv.submit(r)
+    while not srv.idle():
+        srv.tick()
+    tol = SERVE_TOL[prec]
+    for r in reqs:
+        n = r.prob["n"]
+        assert r.status == "done", r.error
+        got = r.result.cpu().numpy()
+        samp = ref[f"n{n}_samples"]
+        g = got[ref[f"n{n}_idx"]]
+        err = np.linalg.norm(g - samp) / np.linalg.norm(samp)
+        emax = float(np.max(np.abs(g - samp)) / np.max(np.abs(samp)))
+        nerr = abs(np.linalg.norm(got) - ref[f"n{n}_norm"]) / ref[f"n{n}_norm"]
+        sub = got.reshape(n, n)[::8, ::8]
+        serr = np.linalg.norm(sub - ref[f"n{n}_sub8"]) / np.linalg.norm(ref[f"n{n}_sub8"])
+        print(f"request {r.rid} n={n} P={r.prob['order']} nt={r.nsteps} {prec}: sampled rel L2 "
+              f"{err:.3e}, max {emax:.3e}, norm {nerr:.3e}, sub-grid {serr:.3e}", flush=True)
+        assert err <= tol and emax <= tol and nerr <= tol and serr <= tol, (n, err, emax, nerr,
+                                                                           serr)

@@ -221,3 +221,41 @@ def test_degenerate_cases():
         ridc_pipelined(p, u0, 2, 4)                        # start-up needs nt >= order - 1
     with pytest.raises(ValueError):
         ridc_pipelined(p, u0, 5, 0)
+
+
+@pytest.mark.parametrize("fe,a", [("advect", 1.3), ("upwind", 0.7), ("upwind", -0.9),
+                                  ("none", 0.0)])
+@pytest.mark.parametrize("order", [1, 2, 4, 5])
+def test_fourier_space_evaluation_equals_vector_oracle(fe, a, order):
+    """The mode-by-mode evaluation of a linear periodic problem (scalar steps in Fourier space)
+    and the vector oracle (stencils, FFT solve with refinement) compute the same RIDC values by
+    different routes; a dropped term, a wrong sign or a misplaced node in either would split
+    them."""
+    from oracle import ridc_linear_periodic
+    p = Problem(dim=1, bc="periodic", n=40, length=2 * math.pi, fe=fe, a=a, nu=0.07, dt=0.02)
+    u0 = workloads.fourier_modes_1d(40, np.random.default_rng(3)) + 0.4
+    nt = 23
+    vec = ridc_sequential(p, u0, nt, order)
+    modal = ridc_linear_periodic(p, u0, nt, order)
+    for j in range(order):
+        assert rel_l2(modal[j], vec[j]) < 1e-13, (j, rel_l2(modal[j], vec[j]))
+
+
+def test_fourier_space_evaluation_closed_forms():
+    """Order 1 on one mode is the forward-backward Euler amplification; the zero mode (the grid
+    sum) is conserved by every level."""
+    from oracle import periodic_mode_symbols, ridc_linear_periodic
+    p = _advdiff(n=64, nt=40)
+    x = np.arange(p.n) * p.h
+    out = ridc_linear_periodic(p, np.sin(3 * x), 40, 1)[0]
+    lam_e, lam_i = _mode_eigs(p, 3)
+    g = ((1 + p.dt * lam_e) / (1 - p.dt * lam_i)) ** 40
+    np.testing.assert_allclose(out, np.imag(g * np.exp(3j * x)), atol=1e-13)
+    le, li = periodic_mode_symbols(p)
+    assert abs(le[3] - lam_e) < 1e-12 and abs(li[3] - lam_i) < 1e-12
+    u0 = 2 + np.cos(2 * x)
+    for o in ridc_linear_periodic(p, u0, 40, 4):
+        assert abs(o.sum() - u0.sum()) < 1e-12 * u0.sum()
+    with pytest.raises(ValueError):
+        periodic_mode_symbols(Problem(dim=1, bc="periodic", n=8, length=1.0, fe="burgers",
+                                      a=0.0, nu=0.1, dt=0.1))
