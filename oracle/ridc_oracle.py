@@ -85,13 +85,18 @@ class Problem:
     a: float
     nu: float
     dt: float
+    # stiff term f^S: "diffusion" (nu Lap_h, linear) or, for the Newton path of
+    # ``oracle.ridc_ext``, diffusion plus a pointwise reaction of rate kappa
+    fi: str = "diffusion"
+    kappa: float = 0.0
 
     @staticmethod
     def from_dict(d: dict, nt: int | None = None) -> "Problem":
         nt = d["nt"] if nt is None else nt
         return Problem(dim=int(d["dim"]), bc=d["bc"], n=int(d["n"]), length=float(d["length"]),
                        fe=d["fe"], a=float(d.get("a", 0.0)), nu=float(d["nu"]),
-                       dt=float(d["T"]) / nt)
+                       dt=float(d["T"]) / nt, fi=d.get("fi", "diffusion"),
+                       kappa=float(d.get("kappa", 0.0)))
 
     @property
     def h(self) -> float:
@@ -247,6 +252,8 @@ def solve_implicit(p: Problem, rhs: np.ndarray) -> np.ndarray:
     the solve of the residual ``rhs - (x - dt f^S(x))`` (plain iterative refinement; the direct
     solvers alone lose up to a few units in the last place per step, which adds up over
     thousands of steps)."""
+    if p.fi != "diffusion":
+        raise ValueError("a nonlinear stiff term needs the Newton solve of oracle.ridc_ext")
     x = _solve_direct(p, rhs)
     res = rhs - (x - p.dt * f_implicit(p, x))
     return x + _solve_direct(p, res)
