@@ -120,6 +120,24 @@ int ridc_integrate(ridc_handle* h, const double* u0_dev, int64_t nsteps, double*
 int ridc_integrate_restarts(ridc_handle* h, const double* u0_dev, int64_t nsteps,
                             int32_t segments, double* uT_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same 1D integration as ridc_create +
+ * ridc_integrate + ridc_destroy, with the same kernels and bitwise the same result, but with no
+ * handle and no allocation of any kind on the device.  The level rings and the weight and PCR
+ * tables live in a fixed 32 MiB array inside the library, one per GPU, which the GPU keeps until
+ * the process ends.  p: as for ridc_create, dim 1 and order <= 6; the rings need
+ * (sum over levels of ring slots) * n * 8 bytes plus 4 KiB, e.g. n <= 246,000 at order 4
+ * (17 slots).  hip_stream: the stream of the work (NULL = null stream).  u0_dev, uT_dev: n
+ * doubles on the current device, owned by the caller, may alias.  nonfinite_dev (nullable):
+ * a device int the caller has cleared, set to 1 when the result holds a NaN or Inf.
+ * Asynchronous; the caller synchronises the stream.  All calls on one GPU share its array:
+ * calls whose work overlaps on that GPU (other streams, other threads) race and give wrong
+ * results; calls in stream order on one stream are safe.  Errors (before any device work):
+ * RIDC_E_INVAL, RIDC_E_UNSUPPORTED (2D, order > 6, or a problem larger than the array),
+ * RIDC_E_HIP.                                                                                */
+int ridc_integrate_noalloc(const ridc_problem* p, void* hip_stream, const double* u0_dev,
+                           int64_t nsteps, double* uT_dev, int* nonfinite_dev);
+
 /* Integrate `count` handles (any mix of sizes, orders, dims and precisions, all created on the
  * same stream) together: each pipeline step of every handle is grouped into shared launches.
  * u0[i], uT[i] and nsteps[i] as in ridc_integrate.  Each handle's result is bitwise the same

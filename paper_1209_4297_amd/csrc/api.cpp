@@ -214,9 +214,12 @@ bool tile_fits(const ridc_problem* p, const PcrPlan& pcr, const Tile1D& t) {
   return 2 * sizeof(double) * (size_t)(t.B + 2 * H) <= (size_t)device_max_lds();
 }
 
-int choose_tile_1d(const ridc_problem* p, const PcrPlan& pcr, Tile1D* out) {
+// allow_fused: a tuned whole-range workgroup may be chosen (otherwise one launch per step)
+int choose_tile_1d(const ridc_problem* p, const PcrPlan& pcr, Tile1D* out,
+                   bool allow_fused = true) {
   Tile1D t;
-  if (tuned_tile(p->n, p->bc, pcr.stages, &t) && tile_fits(p, pcr, t)) {
+  if (tuned_tile(p->n, p->bc, pcr.stages, &t) && (allow_fused || !t.fused) &&
+      tile_fits(p, pcr, t)) {
     *out = t;
     return RIDC_OK;
   }
@@ -1097,6 +1100,94 @@ int ridc_integrate_restarts(ridc_handle* h, const double* u0_dev, int64_t nsteps
     if (rc != RIDC_OK) return rc;
     src = uT_dev;
   }
+  return RIDC_OK;
+}
+
+int ridc_integrate_noalloc(const ridc_problem* p, void* hip_stream, const double* u0_dev,
+                           int64_t nsteps, double* uT_dev, int* nonfinite_dev) {
+  int rc = validate(p);
+  if (rc != RIDC_OK) return rc;
+  if (p->dim != 1) return fail(RIDC_E_UNSUPPORTED, "the allocation-free integration is 1D only");
+  if (p->order > kNoAllocMaxOrder)
+    return fail(RIDC_E_UNSUPPORTED, "the allocation-free integration covers orders up to 6");
+  if (!u0_dev || !uT_dev) return fail(RIDC_E_INVAL, "NULL u0 or uT");
+  if (nsteps < 0) return fail(RIDC_E_INVAL, "nsteps must be >= 0");
+  if (nsteps > 0 && nsteps < p->order - 1)
+    return fail(RIDC_E_INVAL, "nsteps must be 0 or >= order-1 (start-up quadrature)");
+  const int P = p->order;
+  const int64_t n = p->n;
+  int64_t slots = 0;
+  for (int j = 0; j < P; ++j) slots += ring_slots(j, P);
+  const size_t need = kNoAllocRingsOffset + sizeof(double) * (size_t)(slots * n);
+  if (need > kNoAllocScratchBytes)
+    return fail(RIDC_E_UNSUPPORTED, "needs " + std::to_string(need) + " bytes of scratch; the "
+                "allocation-free integration holds " + std::to_string(kNoAllocScratchBytes));
+  PcrPlan pcr;
+  Tile1D tile;
+  const double h = grid_h(p);
+  const int64_t M = p->bc == RIDC_BC_PERIODIC ? n : 2 * n + 2;
+  if (!pcr_plan(p->dt * p->nu / (h * h), M, &pcr))
+    return fail(RIDC_E_UNSUPPORTED, "PCR did not converge within the stage cap");
+  rc = choose_tile_1d(p, pcr, &tile, /*allow_fused=*/false);
+  if (rc != RIDC_OK) return rc;
+  void* base = nullptr;
+  rc = noalloc_scratch(&base);
+  if (rc != RIDC_OK) return rc;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const size_t bytes = sizeof(double) * (size_t)n;
+  if (nsteps == 0) {
+    RIDC_HIP_TRY(hipMemcpyAsync(uT_dev, u0_dev, bytes, hipMemcpyDeviceToDevice, stream));
+    if (nonfinite_dev) RIDC_HIP_TRY(launch_nonfinite_check(uT_dev, n, nonfinite_dev, stream));
+    return RIDC_OK;
+  }
+  // the scratch array: tables, then the level rings (layout as in a handle's pool)
+  char* b = static_cast<char*>(base);
+  NoAllocTables t{};
+  double* W[kNoAllocMaxOrder] = {};
+  double* ring[kNoAllocMaxOrder] = {};
+  int R[kNoAllocMaxOrder] = {};
+  double* wdev = reinterpret_cast<double*>(b + kNoAllocWeightsOffset);
+  for (int j = 1; j < P; ++j) {
+    W[j] = wdev + t.nw;
+    for (int r = 0; r < j; ++r) {
+      quadrature_weights(j, r, t.w + t.nw);
+      t.nw += j + 1;
+    }
+  }
+  t.stages = pcr.stages;
+  for (int k = 0; k < pcr.stages; ++k) {
+    t.gamma[k] = pcr.gamma[k];
+    t.shift[k] = (int32_t)pcr.shift[k];
+  }
+  double* rp = reinterpret_cast<double*>(b + kNoAllocRingsOffset);
+  for (int j = 0; j < P; ++j) {
+    R[j] = ring_slots(j, P);
+    ring[j] = rp;
+    rp += (int64_t)R[j] * n;
+  }
+  RIDC_HIP_TRY(launch_noalloc_tables(t, base, stream));
+  // every level starts from the initial data (section III-E, Fig. 2): slot 0 of each ring
+  for (int j = 0; j < P; ++j)
+    RIDC_HIP_TRY(hipMemcpyAsync(ring[j], u0_dev, bytes, hipMemcpyDeviceToDevice, stream));
+  Solo1D a{};
+  fill_solo(*p, h, pcr, tile, ring, R, W,
+            reinterpret_cast<const double*>(b + kNoAllocGammaOffset),
+            reinterpret_cast<const int32_t*>(b + kNoAllocShiftOffset), nsteps, &a);
+  Lvl1D probe{};
+  probe.n = (int32_t)n;
+  probe.bc = p->bc;
+  probe.wrap = tile.wrap;
+  probe.B = a.B;
+  probe.H = a.H;
+  const size_t lds = lds_bytes_1d(probe);
+  RIDC_HIP_TRY(prepare_1d_step(tile.threads, P, lds));
+  const int64_t total = pipeline_steps(nsteps, P);
+  for (int64_t s = 1; s <= total; ++s)
+    RIDC_HIP_TRY(launch_1d_solo(a, P * a.nchunks, tile.threads, P, lds, s, stream));
+  const int top = P - 1;
+  RIDC_HIP_TRY(hipMemcpyAsync(uT_dev, ring[top] + (nsteps % R[top]) * n, bytes,
+                              hipMemcpyDeviceToDevice, stream));
+  if (nonfinite_dev) RIDC_HIP_TRY(launch_nonfinite_check(uT_dev, n, nonfinite_dev, stream));
   return RIDC_OK;
 }
 

@@ -156,4 +156,30 @@ hipError_t launch_nonfinite_check(const double* x, int64_t count, int* flag, hip
 // LDS bytes a 1D item needs.
 size_t lds_bytes_1d(const Lvl1D& it);
 
+// ---------------------------------------------------------------------------------------------
+// allocation-free 1D integration (noalloc.hip): a fixed scratch array per GPU
+// ---------------------------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;   // 32 MiB per GPU
+constexpr int kNoAllocMaxOrder = 6;
+constexpr int kNoAllocWeights = 70;          // sum of j(j+1) over j = 1..5
+constexpr size_t kNoAllocWeightsOffset = 0;
+constexpr size_t kNoAllocGammaOffset = 1024;
+constexpr size_t kNoAllocShiftOffset = 1536;
+constexpr size_t kNoAllocRingsOffset = 4096;
+
+// Tables written into the scratch array by one small kernel (passed by value, so the call
+// needs no host staging buffer).
+struct NoAllocTables {
+  double w[kNoAllocWeights];   // weights of levels 1..P-1, level after level (j rows of j+1)
+  double gamma[kMaxPcr];
+  int32_t shift[kMaxPcr];
+  int32_t nw, stages;
+};
+
+// Device address of this GPU's scratch array (looked up once per device, on first use).
+int noalloc_scratch(void** ptr);
+
+// Write the weight and PCR tables into the scratch array at `base`.
+hipError_t launch_noalloc_tables(const NoAllocTables& t, void* base, hipStream_t stream);
+
 }  // namespace ridc

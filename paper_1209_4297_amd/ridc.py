@@ -83,6 +83,8 @@ def _load():
                                                   ctypes.POINTER(ctypes.c_double)]),
         "ridc_autotune_batch": (ctypes.c_int, [ctypes.POINTER(vp), i32, ctypes.POINTER(i32),
                                                ctypes.POINTER(i32)]),
+        "ridc_integrate_noalloc": (ctypes.c_int, [ctypes.POINTER(Problem), vp, dp, i64, dp,
+                                                  vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -97,7 +99,8 @@ EXPORTED = ("ridc_create", "ridc_destroy", "ridc_footprint_bytes", "ridc_integra
             "ridc_sync", "ridc_last_error", "ridc_quadrature_weights", "ridc_pcr_plan",
             "ridc_step_cost", "ridc_version", "ridc_autotune", "ridc_set_tile",
             "ridc_kernel_time", "ridc_integrate_restarts", "ridc_set_batch_tile",
-            "ridc_autotune_batch", "ridc_batch_kernel_time", "ridc_stencil_time")
+            "ridc_autotune_batch", "ridc_batch_kernel_time", "ridc_stencil_time",
+            "ridc_integrate_noalloc")
 
 
 def lib():
@@ -297,6 +300,25 @@ def batch_kernel_time(solvers, reps: int):
     return us.value, b.value
 
 
+def integrate_noalloc(prob: dict, u0, nsteps: int, uT=None, nonfinite=None, dt=None,
+                      stream=None):
+    """1D integration through ``ridc_integrate_noalloc`` (no device allocation by the
+    library; its fixed per-GPU array holds the rings).  ``nonfinite`` (optional): a cleared
+    int32 CUDA tensor set to 1 when the result holds a NaN or Inf.  Asynchronous."""
+    import torch
+    if uT is None:
+        uT = torch.empty_like(u0)
+    p = make_problem(prob, dt)
+    flag = None
+    if nonfinite is not None:
+        if not (nonfinite.is_cuda and nonfinite.dtype == torch.int32):
+            raise TypeError("nonfinite must be an int32 CUDA tensor")
+        flag = ctypes.c_void_p(nonfinite.data_ptr())
+    _check(_lib.ridc_integrate_noalloc(ctypes.byref(p), _stream_ptr(stream), _ptr(u0),
+                                       int(nsteps), _ptr(uT), flag))
+    return uT
+
+
 def pipeline_steps(nt: int, order: int) -> int:
     return nt + order * (order - 1) // 2 if nt > 0 else 0
 
@@ -307,7 +329,7 @@ def grid_h(prob: dict) -> float:
 
 
 __all__ = ["Ridc", "RidcError", "advance", "integrate_batch", "set_batch_tile", "autotune_batch",
-           "batch_kernel_time",
+           "batch_kernel_time", "integrate_noalloc",
            "make_problem", "footprint_bytes",
            "quadrature_weights", "pcr_plan", "pipeline_steps", "library_path", "lib", "EXPORTED",
            "math"]

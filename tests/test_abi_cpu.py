@@ -129,3 +129,28 @@ def test_batch_tile_validation(ridc):
     for threads, rows in [(1024, 768), (512, 0), (256, 0)]:
         assert lib.ridc_set_batch_tile(threads, rows) == 0
     assert lib.ridc_autotune_batch(None, 1, None, None) == ridc.RIDC_E_INVAL
+
+
+def test_noalloc_rejects_before_any_device_work(ridc):
+    """The allocation-free entry point checks its arguments and the size of its fixed array on
+    the host first: these calls return before any pointer is touched (no GPU needed)."""
+    import ctypes
+    lib = ridc.lib()
+    fake = ctypes.c_void_p(0x1000)     # never dereferenced: every case fails on the host
+    base = dict(dim=1, bc="periodic", n=128, length=2 * math.pi, fe="advect", order=4, a=1.0,
+                nu=0.1, T=1.0, nt=200)
+    cases = [
+        (dict(base, n=1 << 20), ridc.RIDC_E_UNSUPPORTED),     # 17 slots x 8 MiB > 32 MiB
+        (dict(base, order=7), ridc.RIDC_E_UNSUPPORTED),
+        (dict(base, dim=2, bc="dirichlet", fe="none", n=64), ridc.RIDC_E_UNSUPPORTED),
+        (dict(base, nu=-1.0), ridc.RIDC_E_INVAL),
+    ]
+    for prob, code in cases:
+        p = ridc.make_problem(prob)
+        rc = lib.ridc_integrate_noalloc(ctypes.byref(p), None, fake, 10, fake, None)
+        assert rc == code, (prob, rc, lib.ridc_last_error())
+    p = ridc.make_problem(base)
+    assert lib.ridc_integrate_noalloc(ctypes.byref(p), None, fake, 2, fake, None) == \
+        ridc.RIDC_E_INVAL                                     # fewer than order-1 steps
+    assert lib.ridc_integrate_noalloc(ctypes.byref(p), None, None, 10, fake, None) == \
+        ridc.RIDC_E_INVAL
