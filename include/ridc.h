@@ -89,6 +89,36 @@ typedef struct {
 
 typedef struct ridc_handle ridc_handle;   /* opaque; owned by the library                     */
 
+/* ---- extensions: a nonlinear stiff term and IMEX Runge-Kutta levels (1D) ------------------- */
+/* Stiff term f^S = nu Lap_h u + kappa g(u).  With a reaction g the implicit equation of every
+ * stage, y - tau f^S(y) = rhs, is nonlinear and is solved by Newton's method (section III-B,
+ * after eq. pred), each iterate a tridiagonal solve with the Jacobian
+ * I - tau (nu D2 + kappa diag g'(y)).                                                         */
+typedef enum {
+  RIDC_FS_DIFFUSION = 0,     /* g = 0 (linear: one solve per stage)                           */
+  RIDC_FS_LOGISTIC = 1,      /* g(u) = u (1 - u)                                              */
+  RIDC_FS_CUBIC = 2          /* g(u) = u - u^3                                                */
+} ridc_fs_kind;
+
+/* IMEX pair of one level (section II; section III-D, Thm 2).  The predictor takes one step of
+ * its pair; a corrector applies its pair to the integral form of the error equation (section
+ * III-A), the previous level interpolated through S_j = p_0 + ... + p_j stored nodes (the
+ * section III-C window widened to S_j nodes), so level j has order S_j.                       */
+typedef enum {
+  RIDC_PAIR_FBE = 0,         /* forward-backward Euler as a two-stage pair, order 1           */
+  RIDC_PAIR_ARK3 = 1,        /* the third-order pair of section II (5 stages)                 */
+  RIDC_PAIR_ARK4 = 2         /* the fourth-order pair of section II (7 stages)                */
+} ridc_pair;
+
+typedef struct {
+  int32_t fs_kind;               /* ridc_fs_kind; a reaction needs a Dirichlet grid            */
+  int32_t newton_maxit;          /* Newton iterates allowed per stage (0 = 30); a stage that
+                                    does not converge leaves NaN (RIDC_E_NONFINITE on sync)    */
+  double kappa;                  /* reaction rate                                             */
+  int32_t pair[RIDC_MAX_ORDER];  /* ridc_pair of level j = 0..order-1 (the predictor first)   */
+  int32_t reserved;              /* must be 0                                                 */
+} ridc_ext;
+
 /* ---- lifetime ------------------------------------------------------------------------------ */
 /* Validate *p, build the plan (exact quadrature weights of section III-C, the pipeline schedule,
  * level rings, solver data) and allocate device memory on the current HIP device.
@@ -96,6 +126,29 @@ typedef struct ridc_handle ridc_handle;   /* opaque; owned by the library       
  * On success *out receives the handle.  Errors: RIDC_E_INVAL, RIDC_E_UNSUPPORTED,
  * RIDC_E_NOMEM, RIDC_E_HIP.                                                                  */
 int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out);
+
+/* ridc_create for a 1D problem whose levels are IMEX pairs and/or whose stiff term carries a
+ * reaction (ridc_ext).  p->order is the number of levels P; level j has order
+ * S_j = p_0 + ... + p_j (Thm 2), and the result, the top level, has order S_{P-1}.  Level j
+ * computes t_m at pipeline step m + d_j, d_0 = 0, d_j = d_{j-1} + S_j - 1 (its first step needs
+ * the previous level through the window's last start-up node); an integration of nt steps takes
+ * nt + d_{P-1} pipeline steps and needs nt = 0 or nt >= S_{P-1} - 1.  Every entry point that
+ * takes a handle accepts the result (tuning entry points: RIDC_E_UNSUPPORTED).  Limits: dim 1,
+ * FP64, n <= 8192, S_{P-1} <= 12.  Errors: as ridc_create, and RIDC_E_UNSUPPORTED for a
+ * reaction on a periodic grid.                                                                */
+int ridc_create_ext(const ridc_problem* p, const ridc_ext* e, void* hip_stream,
+                    ridc_handle** out);
+
+/* Device bytes ridc_create_ext would allocate (0 if invalid).                                 */
+size_t ridc_footprint_bytes_ext(const ridc_problem* p, const ridc_ext* e);
+
+/* Interpolation and partial-interval quadrature weights of an IMEX corrector stage (section
+ * III-C with S nodes): for the window of S equispaced nodes whose position r (0 <= r <= S-2)
+ * holds t_n, interp[k] = l_k(t_n + c dt) and quad[k] = (1/dt) int_{t_n}^{t_n + c dt} l_k, with
+ * c the abscissa of stage `stage` of `pair` and l_k the Lagrange basis (k = 0..S-1, ascending
+ * nodes); exact rationals rounded once.  2 <= S <= 12.  Host only.                          */
+int ridc_stage_weights(int32_t S, int32_t r, int32_t pair, int32_t stage, double* interp,
+                       double* quad);
 
 /* Free everything the handle owns (after synchronising its stream).  NULL-safe.              */
 int ridc_destroy(ridc_handle* h);

@@ -74,6 +74,16 @@ struct ridc_handle {
   // 2D plan
   Plan2D* p2 = nullptr;
 
+  // IMEX levels (ridc_create_ext): pairs, orders, delays, f rings and the level-step items
+  bool imex = false;
+  ridc_ext ext{};
+  std::vector<int> S;           // order of level j: p_0 + .. + p_j (also its window nodes)
+  std::vector<int64_t> delay;   // level j computes t_m at pipeline step m + delay[j]
+  std::vector<double*> ringF;   // f^S + f^N of the stored values (levels below the top)
+  std::vector<ImexLvl> iproto;  // one item per level (sigma0 = 0)
+  ImexLvl* d_imex = nullptr;    // device copy (inside the pool)
+  int imex_M = 2, imex_T = 64;
+
   // graph of a whole integration, cached per nt
   hipGraphExec_t gexec = nullptr;
   int64_t graph_nt = -1;
@@ -385,6 +395,9 @@ struct BatchArena {
   CopyItem* d_copy = nullptr;
   CopyItem* h_copy = nullptr;
   size_t cap_copy = 0;
+  ImexLvl* d_imex = nullptr;
+  ImexLvl* h_imex = nullptr;
+  size_t cap_imex = 0;
   hipEvent_t done = nullptr;
   bool pending = false;
   hipEvent_t used = nullptr;
@@ -424,6 +437,25 @@ int arena_reserve_fused(size_t n) {
     if (hipHostMalloc(&g_arena.h_fused, cap * sizeof(Fused1D), hipHostMallocDefault) != hipSuccess)
       return fail(RIDC_E_NOMEM, "batch fused staging");
     g_arena.cap_fused = cap;
+  }
+  return RIDC_OK;
+}
+
+int arena_reserve_imex(size_t n) {
+  // called after arena_reserve (device, events and pending upload handled there)
+  if (n > g_arena.cap_imex) {
+    int rc = arena_drain();
+    if (rc != RIDC_OK) return rc;
+    if (g_arena.d_imex) (void)hipFree(g_arena.d_imex);
+    if (g_arena.h_imex) (void)hipHostFree(g_arena.h_imex);
+    g_arena.d_imex = nullptr;
+    g_arena.h_imex = nullptr;
+    const size_t cap = std::max<size_t>(n, 2 * g_arena.cap_imex);
+    if (hipMalloc(&g_arena.d_imex, cap * sizeof(ImexLvl)) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "batch IMEX table");
+    if (hipHostMalloc(&g_arena.h_imex, cap * sizeof(ImexLvl), hipHostMallocDefault) != hipSuccess)
+      return fail(RIDC_E_NOMEM, "batch IMEX staging");
+    g_arena.cap_imex = cap;
   }
   return RIDC_OK;
 }
@@ -476,6 +508,28 @@ int arena_reserve(size_t nitems, size_t nblocks, hipStream_t stream) {
 
 int64_t pipeline_steps(int64_t nt, int P) { return nt > 0 ? nt + (int64_t)P * (P - 1) / 2 : 0; }
 
+// Pipeline steps of an integration of nt steps on this handle, and the first step at which
+// every level is active.
+int64_t handle_steps(const ridc_handle* h, int64_t nt) {
+  if (h->imex) return nt > 0 ? nt + h->delay[h->P - 1] : 0;
+  return pipeline_steps(nt, h->P);
+}
+int64_t first_full_step(const ridc_handle* h) {
+  return h->imex ? h->delay[h->P - 1] + 1 : (int64_t)h->P * (h->P - 1) / 2 + 1;
+}
+
+// IMEX handles: the first launch of an integration also writes f of every level's initial
+// value (the windows' node t_0).
+int launch_imex_steps(ridc_handle* h, int64_t first, int64_t last) {
+  const bool per = h->p.bc == RIDC_BC_PERIODIC;
+  if (first == 1)
+    RIDC_HIP_TRY(launch_imex1d(h->d_imex, h->P, h->imex_M, h->imex_T, per, 0, true, h->stream));
+  for (int64_t s = first; s <= last; ++s)
+    RIDC_HIP_TRY(launch_imex1d(h->d_imex, h->P, h->imex_M, h->imex_T, per, s, false,
+                               h->stream));
+  return RIDC_OK;
+}
+
 // The step count travels in the kernel arguments (single instance) or in the batch tables, so
 // arming a 1D handle touches host state only; the device item copy holds the PCR coefficients.
 void arm_solo_items(ridc_handle* h) {
@@ -502,6 +556,7 @@ int launch_fused_steps(ridc_handle* h, int64_t first, int64_t last) {
 }
 
 int run_solo_steps(ridc_handle* h, int64_t first, int64_t last) {
+  if (h->imex) return launch_imex_steps(h, first, last);
   if (h->p.dim == 1 && h->fused) return launch_fused_steps(h, first, last);
   if (h->p.dim == 1) return launch_solo_steps_1d(h, first, last);
   Plan2D* pl = h->p2;
@@ -689,11 +744,21 @@ int stage_batch_1d(const std::vector<ridc_handle*>& hs, const BatchTile& bt, boo
 int arm_handle(ridc_handle* h, const double* u0_dev, int64_t nsteps) {
   if (!h || !u0_dev) return fail(RIDC_E_INVAL, "NULL handle or u0");
   if (nsteps < 0) return fail(RIDC_E_INVAL, "nsteps must be >= 0");
-  if (nsteps > 0 && nsteps < h->P - 1)
-    return fail(RIDC_E_INVAL, "nsteps must be 0 or >= order-1 (start-up quadrature)");
+  const int64_t least = h->imex ? (h->P > 1 ? h->S[h->P - 1] - 1 : 0) : h->P - 1;
+  if (nsteps > 0 && nsteps < least)
+    return fail(RIDC_E_INVAL, "nsteps must be 0 or at least the start-up window of the top "
+                "corrector (order-1 nodes)");
   h->nt = nsteps;
   h->sigma = 0;
-  h->total = pipeline_steps(nsteps, h->P);
+  h->total = handle_steps(h, nsteps);
+  if (h->imex) {
+    for (auto& it : h->iproto) it.nt = nsteps;
+    RIDC_HIP_TRY(hipMemcpyAsync(h->d_imex, h->iproto.data(), sizeof(ImexLvl) * h->P,
+                                hipMemcpyHostToDevice, h->stream));
+    // the host items are rewritten by the next arm: wait for this upload
+    RIDC_HIP_TRY(hipStreamSynchronize(h->stream));
+    return RIDC_OK;
+  }
   if (h->p.dim == 1) {
     arm_solo_items(h);
     return RIDC_OK;
@@ -735,6 +800,121 @@ int stage_copies(const std::vector<CopyItem>& c, hipStream_t stream) {
     RIDC_HIP_TRY(launch_copy_items(g_arena.d_copy + off, cnt, most, stream));
   }
   return arena_release(stream);
+}
+
+// ---------------------------------------------------------------------------------------------
+// IMEX levels (ridc_create_ext): Thm 2's ARK-based RIDC and Newton for a nonlinear stiff term
+// ---------------------------------------------------------------------------------------------
+struct ImexPlan {
+  std::vector<ImexPair> pair;   // per level
+  std::vector<int> S;           // order of level j = window nodes of corrector j
+  std::vector<int64_t> delay;
+  std::vector<int> R;           // ring slots of the values (and of f, below the top)
+  size_t rings = 0, frings = 0, weights = 0, work = 0, items = 0, total = 0;
+  int M = 2, T = 64;
+};
+
+int validate_ext(const ridc_problem* p, const ridc_ext* e, ImexPlan* out) {
+  int rc = validate(p);
+  if (rc != RIDC_OK) return rc;
+  if (!e) return fail(RIDC_E_INVAL, "ext is NULL");
+  if (p->dim != 1) return fail(RIDC_E_UNSUPPORTED, "IMEX levels and stiff reactions are 1D");
+  if (p->n > (int64_t)kImexMaxThreads * kImexMaxRows)
+    return fail(RIDC_E_UNSUPPORTED, "IMEX levels take n <= 8192");
+  if (e->reserved != 0) return fail(RIDC_E_INVAL, "ext.reserved must be 0");
+  if (e->fs_kind < RIDC_FS_DIFFUSION || e->fs_kind > RIDC_FS_CUBIC)
+    return fail(RIDC_E_INVAL, "unknown stiff term");
+  if (e->fs_kind != RIDC_FS_DIFFUSION && p->bc != RIDC_BC_DIRICHLET0)
+    return fail(RIDC_E_UNSUPPORTED, "a stiff reaction needs a Dirichlet grid");
+  if (!std::isfinite(e->kappa)) return fail(RIDC_E_INVAL, "kappa must be finite");
+  if (e->newton_maxit < 0 || e->newton_maxit > 1000)
+    return fail(RIDC_E_INVAL, "newton_maxit must be in 0..1000");
+  ImexPlan pl;
+  const int P = p->order;
+  int acc = 0;
+  for (int j = 0; j < P; ++j) {
+    ImexPair pr;
+    if (!imex_pair(e->pair[j], &pr)) return fail(RIDC_E_INVAL, "unknown pair of a level");
+    // stage 0 explicit at c = 0, every later stage implicit (true of every pair of section II)
+    if (pr.AS[0][0] != 0.0 || pr.c6[0] != 0) return fail(RIDC_E_UNSUPPORTED, "pair shape");
+    for (int i = 1; i < pr.s; ++i)
+      if (pr.AS[i][i] == 0.0) return fail(RIDC_E_UNSUPPORTED, "pair shape");
+    acc += pr.order;
+    pl.pair.push_back(pr);
+    pl.S.push_back(acc);
+  }
+  if (acc > kMaxOrder) return fail(RIDC_E_UNSUPPORTED, "the top level's order exceeds 12");
+  pl.delay.assign(P, 0);
+  for (int j = 1; j < P; ++j) pl.delay[j] = pl.delay[j - 1] + pl.S[j] - 1;
+  pl.R.resize(P);
+  for (int j = 0; j < P; ++j) pl.R[j] = j + 1 < P ? 2 * pl.S[j + 1] - 1 : 2;
+  const size_t vec = sizeof(double) * (size_t)p->n;
+  for (int j = 0; j < P; ++j) {
+    pl.rings += vec * pl.R[j];
+    if (j + 1 < P) pl.frings += vec * pl.R[j];
+    if (j > 0)
+      pl.weights += sizeof(double) * (size_t)(pl.S[j] - 1) * pl.pair[j].s * 2 * pl.S[j];
+    pl.work += vec * 2 * pl.pair[j].s;
+  }
+  pl.rings = align256(pl.rings);
+  pl.frings = align256(pl.frings);
+  pl.weights = align256(std::max<size_t>(pl.weights, 8));
+  pl.work = align256(pl.work);
+  pl.items = align256(sizeof(ImexLvl) * P);
+  pl.total = pl.rings + pl.frings + pl.weights + pl.work + pl.items + 256;   // + flag
+  imex_shape(p->n, &pl.M, &pl.T);
+  if (out) *out = pl;
+  return RIDC_OK;
+}
+
+// One grouped launch per pipeline step for IMEX handles of one shape class (rows per thread,
+// threads, boundary kind): every level of every handle in one table, each handle's own step
+// = launch step + its current sigma.  Handles at their first step also get the launch that
+// writes f of the initial values (harmless for the others: f of a stored value, rewritten).
+int advance_imex(const std::vector<ridc_handle*>& hs, int64_t max_steps, hipStream_t stream) {
+  std::vector<ridc_handle*> rest = hs;
+  while (!rest.empty()) {
+    const ridc_handle* k = rest[0];
+    std::vector<ridc_handle*> grp, other;
+    for (auto* h : rest)
+      (h->imex_M == k->imex_M && h->imex_T == k->imex_T && h->p.bc == k->p.bc ? grp : other)
+          .push_back(h);
+    rest.swap(other);
+    size_t nitems = 0;
+    for (auto* h : grp) nitems += h->P;
+    int rc = arena_reserve(1, 1, stream);
+    if (rc != RIDC_OK) return rc;
+    rc = arena_reserve_imex(nitems);
+    if (rc != RIDC_OK) return rc;
+    size_t q = 0;
+    bool init = false;
+    int64_t steps = 0;
+    for (auto* h : grp) {
+      init = init || h->sigma == 0;
+      steps = std::max(steps, std::min(max_steps, h->total - h->sigma));
+      for (int j = 0; j < h->P; ++j) {
+        ImexLvl L = h->iproto[j];
+        L.nt = h->nt;
+        L.sigma0 = -h->sigma;
+        g_arena.h_imex[q++] = L;
+      }
+    }
+    RIDC_HIP_TRY(hipMemcpyAsync(g_arena.d_imex, g_arena.h_imex, sizeof(ImexLvl) * nitems,
+                                hipMemcpyHostToDevice, stream));
+    RIDC_HIP_TRY(hipEventRecord(g_arena.done, stream));
+    g_arena.pending = true;
+    const bool per = k->p.bc == RIDC_BC_PERIODIC;
+    if (init)
+      RIDC_HIP_TRY(launch_imex1d(g_arena.d_imex, (int)nitems, k->imex_M, k->imex_T, per, 0, true,
+                                 stream));
+    for (int64_t st = 1; st <= steps; ++st)
+      RIDC_HIP_TRY(launch_imex1d(g_arena.d_imex, (int)nitems, k->imex_M, k->imex_T, per, st,
+                                 false, stream));
+    rc = arena_release(stream);
+    if (rc != RIDC_OK) return rc;
+    for (auto* h : grp) h->sigma += std::min(max_steps, h->total - h->sigma);
+  }
+  return RIDC_OK;
 }
 
 }  // namespace
@@ -895,6 +1075,144 @@ int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out) {
   return RIDC_OK;
 }
 
+size_t ridc_footprint_bytes_ext(const ridc_problem* p, const ridc_ext* e) {
+  ImexPlan pl;
+  if (validate_ext(p, e, &pl) != RIDC_OK) return 0;
+  return pl.total;
+}
+
+int ridc_stage_weights(int32_t S, int32_t r, int32_t pair, int32_t stage, double* interp,
+                       double* quad) {
+  ImexPair pr;
+  if (!interp || !quad) return fail(RIDC_E_INVAL, "NULL output");
+  if (!imex_pair(pair, &pr)) return fail(RIDC_E_INVAL, "unknown pair");
+  if (stage < 0 || stage >= pr.s) return fail(RIDC_E_INVAL, "stage out of range");
+  if (!stage_weights(S, r, pr.c6[stage], interp, quad))
+    return fail(RIDC_E_INVAL, "need 2 <= S <= 12 and 0 <= r <= S-2");
+  return RIDC_OK;
+}
+
+int ridc_create_ext(const ridc_problem* p, const ridc_ext* e, void* hip_stream,
+                    ridc_handle** out) {
+  if (!out) return fail(RIDC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  ImexPlan pl;
+  int rc = validate_ext(p, e, &pl);
+  if (rc != RIDC_OK) return rc;
+  auto* h = new ridc_handle();
+  h->p = *p;
+  h->ext = *e;
+  h->imex = true;
+  h->stream = (hipStream_t)hip_stream;
+  h->P = p->order;
+  h->npts = p->n;
+  h->h = grid_h(p);
+  h->S = pl.S;
+  h->delay = pl.delay;
+  h->R = pl.R;
+  h->imex_M = pl.M;
+  h->imex_T = pl.T;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(RIDC_E_HIP, "hipGetDevice failed");
+  }
+  if (hipMalloc(&h->pool, pl.total) != hipSuccess) {
+    (void)hipGetLastError();
+    delete h;
+    return fail(RIDC_E_NOMEM, "device allocation of " + std::to_string(pl.total) + " bytes failed");
+  }
+  h->pool_bytes = pl.total;
+  const int P = h->P;
+  const int64_t n = p->n;
+  char* cur = h->pool;
+  double* rp = (double*)cur;
+  cur += pl.rings;
+  double* fp = (double*)cur;
+  cur += pl.frings;
+  double* wp = (double*)cur;
+  cur += pl.weights;
+  double* kp = (double*)cur;
+  cur += pl.work;
+  h->d_imex = (ImexLvl*)cur;
+  cur += pl.items;
+  h->flag = (int*)cur;
+  h->ring.assign(P, nullptr);
+  h->ringF.assign(P, nullptr);
+  for (int j = 0; j < P; ++j) {
+    h->ring[j] = rp;
+    rp += (int64_t)h->R[j] * n;
+    if (j + 1 < P) {
+      h->ringF[j] = fp;
+      fp += (int64_t)h->R[j] * n;
+    }
+  }
+  // corrector weights: [row r][stage i][interp S, quad S], exact rationals rounded once
+  std::vector<double> w;
+  std::vector<int64_t> woff(P, 0);
+  for (int j = 1; j < P; ++j) {
+    woff[j] = (int64_t)w.size();
+    const int S = h->S[j];
+    for (int r = 0; r <= S - 2; ++r)
+      for (int i = 0; i < pl.pair[j].s; ++i) {
+        double li[kMaxOrder], qi[kMaxOrder];
+        stage_weights(S, r, pl.pair[j].c6[i], li, qi);
+        w.insert(w.end(), li, li + S);
+        w.insert(w.end(), qi, qi + S);
+      }
+  }
+  if (!w.empty() &&
+      hipMemcpy(wp, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    ridc_destroy(h);
+    return fail(RIDC_E_HIP, "weight upload failed");
+  }
+  if (hipMemset(h->flag, 0, sizeof(int)) != hipSuccess) {
+    ridc_destroy(h);
+    return fail(RIDC_E_HIP, "flag init failed");
+  }
+  const double hh = h->h;
+  h->iproto.assign(P, ImexLvl{});
+  for (int j = 0; j < P; ++j) {
+    ImexLvl& L = h->iproto[j];
+    const ImexPair& pr = pl.pair[j];
+    L.own = h->ring[j];
+    L.ownF = h->ringF[j];
+    L.prev = j > 0 ? h->ring[j - 1] : nullptr;
+    L.prevF = j > 0 ? h->ringF[j - 1] : nullptr;
+    L.wt = j > 0 ? wp + woff[j] : nullptr;
+    L.ks = kp;
+    kp += (int64_t)2 * pr.s * n;
+    L.nt = 0;
+    L.sigma0 = 0;
+    L.delay = h->delay[j];
+    L.n = (int32_t)n;
+    L.j = j;
+    L.s = pr.s;
+    L.S = h->S[j];
+    L.R_own = h->R[j];
+    L.R_prev = j > 0 ? h->R[j - 1] : 1;
+    L.bc = p->bc;
+    L.fe = p->fe_kind;
+    L.fs = e->fs_kind;
+    L.maxit = e->newton_maxit > 0 ? e->newton_maxit : 30;
+    L.dt = p->dt;
+    L.ce = explicit_coeff(p->fe_kind, p->a, hh);
+    L.nu_h2 = p->nu / (hh * hh);
+    L.kappa = e->fs_kind == RIDC_FS_DIFFUSION ? 0.0 : e->kappa;
+    for (int i = 0; i < kMaxStages; ++i)
+      for (int l = 0; l < kMaxStages; ++l) {
+        L.AS[i][l] = i < pr.s && l < pr.s ? pr.AS[i][l] : 0.0;
+        L.AN[i][l] = i < pr.s && l < pr.s ? pr.AN[i][l] : 0.0;
+      }
+  }
+  if (hipMemcpy(h->d_imex, h->iproto.data(), sizeof(ImexLvl) * P, hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    ridc_destroy(h);
+    return fail(RIDC_E_HIP, "item table upload failed");
+  }
+  *out = h;
+  return RIDC_OK;
+}
+
 int ridc_destroy(ridc_handle* h) {
   if (!h) return RIDC_OK;
   (void)hipStreamSynchronize(h->stream);
@@ -941,10 +1259,14 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
     return RIDC_OK;
   }
   // ---- 1D handles: one grouped launch per pipeline step --------------------------------------
-  std::vector<ridc_handle*> h1, h2;
+  std::vector<ridc_handle*> h1, h2, h3;
   for (int32_t i = 0; i < count; ++i) {
     if (hs[i]->total - hs[i]->sigma <= 0) continue;
-    (hs[i]->p.dim == 1 ? h1 : h2).push_back(hs[i]);
+    (hs[i]->imex ? h3 : hs[i]->p.dim == 1 ? h1 : h2).push_back(hs[i]);
+  }
+  if (!h3.empty()) {
+    rc = advance_imex(h3, max_steps, stream);
+    if (rc != RIDC_OK) return rc;
   }
   // fused-eligible 1D handles: one workgroup each, every requested step in one launch
   {
@@ -1227,6 +1549,7 @@ int ridc_integrate_batch(ridc_handle* const* hs, int32_t count, const double* co
 
 int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags) {
   if (!h) return fail(RIDC_E_INVAL, "NULL handle");
+  if (h->imex) return fail(RIDC_E_UNSUPPORTED, "IMEX levels have one launch shape per n");
   if (h->p.dim != 1) return fail(RIDC_E_UNSUPPORTED, "tiles are chosen per system in 1D only");
   if (rows < 0 || (flags & ~3)) return fail(RIDC_E_INVAL, "bad rows or flags");
   if (flags & 2) {
@@ -1239,6 +1562,7 @@ int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags) 
 
 int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out) {
   if (!h) return fail(RIDC_E_INVAL, "NULL handle");
+  if (h->imex) return fail(RIDC_E_UNSUPPORTED, "IMEX levels have one launch shape per n");
   if (h->p.dim != 1) {
     if (threads_out) *threads_out = 512;
     if (rows_out) *rows_out = 128;
@@ -1304,7 +1628,7 @@ int ridc_autotune_batch(ridc_handle* const* hs, int32_t count, int32_t* threads_
   if (rc != RIDC_OK) return rc;
   std::vector<ridc_handle*> h1;
   for (int32_t i = 0; i < count; ++i)
-    if (hs[i]->p.dim == 1) h1.push_back(hs[i]);
+    if (hs[i]->p.dim == 1 && !hs[i]->imex) h1.push_back(hs[i]);
   BatchTile best;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1378,7 +1702,8 @@ int ridc_batch_kernel_time(ridc_handle* const* hs, int32_t count, int32_t reps,
   double bytes = 0;
   for (int32_t i = 0; i < count; ++i) {
     ridc_handle* h = hs[i];
-    if (h->p.dim != 1) return fail(RIDC_E_UNSUPPORTED, "grouped 1D launches only");
+    if (h->p.dim != 1 || h->imex)
+      return fail(RIDC_E_UNSUPPORTED, "grouped 1D launches only");
     if (h->nt < 0) return fail(RIDC_E_STATE, "handle not armed");
     if (h->fused) return fail(RIDC_E_UNSUPPORTED, "handle uses the whole-range workgroup");
     const int64_t first_full = (int64_t)h->P * (h->P - 1) / 2 + 1;
@@ -1448,7 +1773,7 @@ int ridc_kernel_time(ridc_handle* h, int32_t reps, double* us_per_launch, double
   if (!h || reps < 1 || !us_per_launch) return fail(RIDC_E_INVAL, "bad arguments");
   if (h->nt < 0) return fail(RIDC_E_STATE, "handle not armed");
   const int64_t s = h->sigma + 1;
-  const int64_t first_full = (int64_t)h->P * (h->P - 1) / 2 + 1;
+  const int64_t first_full = first_full_step(h);
   if (s < first_full || s - first_full + 1 > h->nt)
     return fail(RIDC_E_STATE, "the next pipeline step does not have every level active");
   double bytes = 0, flops = 0;
@@ -1459,6 +1784,28 @@ int ridc_kernel_time(ridc_handle* h, int32_t reps, double* us_per_launch, double
     if (rc != RIDC_OK) return rc;
     const int passes = h->p.prec == RIDC_PREC_FP64 ? 4 : 8;
     if (work_per_launch) *work_per_launch = flops / passes;   // one pass over every level
+    return RIDC_OK;
+  }
+  if (h->imex) {
+    // `reps` launches of the same step: each recomputes the same values (every level reads
+    // only slots that no level of this step writes)
+    const bool per = h->p.bc == RIDC_BC_PERIODIC;
+    hipEvent_t a, b;
+    RIDC_HIP_TRY(hipEventCreate(&a));
+    RIDC_HIP_TRY(hipEventCreate(&b));
+    hipError_t e = launch_imex1d(h->d_imex, h->P, h->imex_M, h->imex_T, per, s, false, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(a, h->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+      e = launch_imex1d(h->d_imex, h->P, h->imex_M, h->imex_T, per, s, false, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(b, h->stream);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return fail(RIDC_E_HIP, std::string("kernel timing: ") + hipGetErrorString(e));
+    *us_per_launch = 1e3 * (double)ms / reps;
+    if (work_per_launch) *work_per_launch = bytes;
     return RIDC_OK;
   }
   if (h->fused) {
@@ -1509,7 +1856,14 @@ int ridc_step_cost(const ridc_handle* h, double* hbm_bytes, double* flops) {
   // steady state, all levels active: level 0 reads its value and writes one; level j >= 1 reads
   // its value and the j+1 window values of level j-1 and writes one
   double vectors = 0;
-  for (int j = 0; j < h->P; ++j) vectors += j == 0 ? 2 : j + 3;
+  if (h->imex) {
+    // IMEX levels: a level reads its value (and, corrector j, the S_j values and S_j stored f of
+    // its window) and writes its value and f (the top level: its value only)
+    for (int j = 0; j < h->P; ++j)
+      vectors += 1 + (j > 0 ? 2 * h->S[j] : 0) + (j + 1 < h->P ? 2 : 1);
+  } else {
+    for (int j = 0; j < h->P; ++j) vectors += j == 0 ? 2 : j + 3;
+  }
   double b = vectors * sizeof(double) * (double)h->npts;
   double f = 0;
   if (h->p.dim == 2) plan2d_cost(h->p2, &b, &f);

@@ -56,6 +56,22 @@ struct PcrPlan {
 };
 bool pcr_plan(double r, int64_t m, PcrPlan* out);
 
+// IMEX pairs (section II) as doubles from exact rationals: s stages, order, the stiff and
+// explicit tableaux and the abscissae (also as multiples of 1/6).
+constexpr int kMaxStages = 7;
+struct ImexPair {
+  int s = 0, order = 0;
+  double AS[kMaxStages][kMaxStages];
+  double AN[kMaxStages][kMaxStages];
+  double c[kMaxStages];
+  int32_t c6[kMaxStages];
+};
+bool imex_pair(int pair, ImexPair* out);
+
+// Lagrange basis on the S nodes 0..S-1 at x = r + c6/6 (interp) and its integral over
+// [r, r + c6/6] (quad), from exact integer arithmetic, rounded once.
+bool stage_weights(int S, int r, int c6, double* interp, double* quad);
+
 // Ring slots of level j in a P-level pipeline: 2j+3 for j < P-1 (the live window that level
 // j+1 reads plus the slot being written), 2 for the top level.
 inline int ring_slots(int j, int P) { return j == P - 1 ? 2 : 2 * j + 3; }
@@ -155,6 +171,39 @@ hipError_t launch_nonfinite_check(const double* x, int64_t count, int* flag, hip
 
 // LDS bytes a 1D item needs.
 size_t lds_bytes_1d(const Lvl1D& it);
+
+// ---------------------------------------------------------------------------------------------
+// IMEX level step (kernels_imex1d.hip): ARK-based RIDC and a nonlinear stiff term, 1D
+// ---------------------------------------------------------------------------------------------
+constexpr int kImexMaxThreads = 512;   // threads per workgroup at most
+constexpr int kImexMaxRows = 16;       // rows per thread at most: n <= 8192
+
+// One (instance, level) work item.  The level computes t_m, m = sigma - sigma0 - delay, at
+// launch step sigma (1 <= m <= nt).
+struct ImexLvl {
+  double* own;            // level values: R_own slots of n
+  double* ownF;           // f^S + f^N of the level values, same slots; null for the top level
+  const double* prev;     // previous level's values (R_prev slots); null for the predictor
+  const double* prevF;    // previous level's f
+  const double* wt;       // corrector weights: [row r = 0..S-2][stage i][interp S, quad S]
+  double* ks;             // stage workspace: K^S_l, K^N_l (l < s-1), then 2 scratch vectors
+  int64_t nt, sigma0, delay;
+  int32_t n, j, s, S;     // unknowns, level, stages of the pair, window nodes (corrector)
+  int32_t R_own, R_prev;
+  int32_t bc, fe, fs, maxit;
+  double dt, ce, nu_h2, kappa;
+  double AS[kMaxStages][kMaxStages];
+  double AN[kMaxStages][kMaxStages];
+};
+
+// Rows per thread (2, 4, 8 or 16) and threads per workgroup (a multiple of 64, at most 512)
+// of the IMEX level step for n unknowns.
+void imex_shape(int64_t n, int* M, int* threads);
+
+// One launch over d_items[0..count) (all of the shape M, threads and of one boundary kind) at
+// launch step sigma; init: instead, write f of every level's initial value (slot 0).
+hipError_t launch_imex1d(const ImexLvl* d_items, int count, int M, int threads, bool periodic,
+                         int64_t sigma, bool init, hipStream_t stream);
 
 // ---------------------------------------------------------------------------------------------
 // allocation-free 1D integration (noalloc.hip): a fixed scratch array per GPU

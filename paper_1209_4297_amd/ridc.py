@@ -44,6 +44,17 @@ class Problem(ctypes.Structure):
     ]
 
 
+FS = {"diffusion": 0, "logistic": 1, "cubic": 2}
+PAIR = {"fbe": 0, "ark3": 1, "ark4": 2}
+
+
+class Ext(ctypes.Structure):
+    _fields_ = [
+        ("fs_kind", ctypes.c_int32), ("newton_maxit", ctypes.c_int32), ("kappa", ctypes.c_double),
+        ("pair", ctypes.c_int32 * 12), ("reserved", ctypes.c_int32),
+    ]
+
+
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"RIDC HIP library not built: {_LIB_PATH} is missing "
@@ -85,6 +96,13 @@ def _load():
                                                ctypes.POINTER(i32)]),
         "ridc_integrate_noalloc": (ctypes.c_int, [ctypes.POINTER(Problem), vp, dp, i64, dp,
                                                   vp]),
+        "ridc_create_ext": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Ext), vp,
+                                           ctypes.POINTER(vp)]),
+        "ridc_footprint_bytes_ext": (ctypes.c_size_t, [ctypes.POINTER(Problem),
+                                                       ctypes.POINTER(Ext)]),
+        "ridc_stage_weights": (ctypes.c_int, [i32, i32, i32, i32,
+                                              ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -100,7 +118,8 @@ EXPORTED = ("ridc_create", "ridc_destroy", "ridc_footprint_bytes", "ridc_integra
             "ridc_step_cost", "ridc_version", "ridc_autotune", "ridc_set_tile",
             "ridc_kernel_time", "ridc_integrate_restarts", "ridc_set_batch_tile",
             "ridc_autotune_batch", "ridc_batch_kernel_time", "ridc_stencil_time",
-            "ridc_integrate_noalloc")
+            "ridc_integrate_noalloc", "ridc_create_ext", "ridc_footprint_bytes_ext",
+            "ridc_stage_weights")
 
 
 def lib():
@@ -126,9 +145,38 @@ def make_problem(prob: dict, dt: float | None = None, prec: str = "fp64") -> Pro
                    nu=float(prob["nu"]), dt=float(dt), prec=PREC[prec], reserved=0)
 
 
+def uses_ext(prob: dict) -> bool:
+    """True for workloads with IMEX levels (``pairs``) or a stiff reaction (``fi``)."""
+    return "pairs" in prob or prob.get("fi", "diffusion") != "diffusion"
+
+
+def make_ext(prob: dict, newton_maxit: int = 0) -> Ext:
+    """ctypes ``ridc_ext`` from a workload dictionary: ``pairs`` (one of fbe/ark3/ark4 per
+    level; default forward-backward Euler everywhere), ``fi`` (diffusion, logistic or cubic:
+    the stiff term nu Lap_h + kappa g) and ``kappa``."""
+    order = int(prob["order"])
+    pairs = prob.get("pairs", ["fbe"] * order)
+    if len(pairs) != order:
+        raise ValueError("one pair per level is needed")
+    arr = (ctypes.c_int32 * 12)(*[PAIR[x] for x in pairs])
+    return Ext(fs_kind=FS[prob.get("fi", "diffusion")], newton_maxit=int(newton_maxit),
+               kappa=float(prob.get("kappa", 0.0)), pair=arr, reserved=0)
+
+
 def footprint_bytes(prob: dict, dt: float | None = None, prec: str = "fp64") -> int:
     p = make_problem(prob, dt, prec)
+    if uses_ext(prob):
+        e = make_ext(prob)
+        return int(_lib.ridc_footprint_bytes_ext(ctypes.byref(p), ctypes.byref(e)))
     return int(_lib.ridc_footprint_bytes(ctypes.byref(p)))
+
+
+def stage_weights(S: int, r: int, pair: str, stage: int):
+    """(interp, quad) weights of an IMEX corrector stage on a window of S nodes."""
+    li = (ctypes.c_double * S)()
+    qi = (ctypes.c_double * S)()
+    _check(_lib.ridc_stage_weights(int(S), int(r), PAIR[pair], int(stage), li, qi))
+    return list(li), list(qi)
 
 
 def quadrature_weights(j: int, r: int):
@@ -164,7 +212,8 @@ def _stream_ptr(stream):
 class Ridc:
     """One RIDC integrator instance (owns its device rings, transforms and workspaces)."""
 
-    def __init__(self, prob: dict, dt: float | None = None, prec: str = "fp64", stream=None):
+    def __init__(self, prob: dict, dt: float | None = None, prec: str = "fp64", stream=None,
+                 newton_maxit: int = 0):
         self.prob = dict(prob)
         self.prec = prec
         self._p = make_problem(prob, dt, prec)
@@ -173,8 +222,13 @@ class Ridc:
         self.side = self._p.n
         self._h = ctypes.c_void_p()
         self._stream = stream
-        _check(_lib.ridc_create(ctypes.byref(self._p), _stream_ptr(stream),
-                                ctypes.byref(self._h)))
+        if uses_ext(prob):
+            self._e = make_ext(prob, newton_maxit)
+            _check(_lib.ridc_create_ext(ctypes.byref(self._p), ctypes.byref(self._e),
+                                        _stream_ptr(stream), ctypes.byref(self._h)))
+        else:
+            _check(_lib.ridc_create(ctypes.byref(self._p), _stream_ptr(stream),
+                                    ctypes.byref(self._h)))
 
     @property
     def handle(self):
@@ -329,7 +383,7 @@ def grid_h(prob: dict) -> float:
 
 
 __all__ = ["Ridc", "RidcError", "advance", "integrate_batch", "set_batch_tile", "autotune_batch",
-           "batch_kernel_time", "integrate_noalloc",
+           "batch_kernel_time", "integrate_noalloc", "make_ext", "uses_ext", "stage_weights",
            "make_problem", "footprint_bytes",
            "quadrature_weights", "pcr_plan", "pipeline_steps", "library_path", "lib", "EXPORTED",
            "math"]

@@ -154,3 +154,44 @@ def test_noalloc_rejects_before_any_device_work(ridc):
         ridc.RIDC_E_INVAL                                     # fewer than order-1 steps
     assert lib.ridc_integrate_noalloc(ctypes.byref(p), None, None, 10, fake, None) == \
         ridc.RIDC_E_INVAL
+
+
+@pytest.mark.parametrize("pair", ["fbe", "ark3", "ark4"])
+def test_stage_weights_are_correctly_rounded(ridc, pair):
+    """The IMEX corrector's interpolation and partial-interval weights (host plan, exact
+    integer arithmetic) are the correctly rounded exact values for every window size, start-up
+    position and stage abscissa."""
+    from oracle import ridc_ext as X
+    tab = X.SCHEMES[pair]
+    for S in range(2, 13):
+        for r in range(S - 1):
+            nodes = list(range(S))
+            for i in range(tab.s):
+                li, qi = ridc.stage_weights(S, r, pair, i)
+                t = Fraction(r) + tab.c[i]
+                lx = X._lagrange_values(nodes, t)
+                qx = lagrange_integral_weights(nodes, Fraction(r), t)
+                assert li == [float(v) for v in lx], (S, r, i)
+                assert qi == [float(v) for v in qx], (S, r, i)
+
+
+def test_ext_validation_and_footprint(ridc):
+    """ridc_create_ext's host checks: reactions need Dirichlet grids, n <= 8192, the top order
+    <= 12; the footprint counts the value and f rings, weights and stage workspaces."""
+    import ctypes
+    lib = ridc.lib()
+    base = dict(dim=1, bc="dirichlet", n=1000, length=1.0, fe="none", order=2, a=0.0, nu=1e-3,
+                T=1.0, nt=100, fi="cubic", kappa=10.0, pairs=["ark3", "fbe"])
+    assert ridc.footprint_bytes(base) > 0
+    assert ridc.footprint_bytes(dict(base, bc="periodic")) == 0
+    assert ridc.footprint_bytes(dict(base, n=8193)) == 0
+    assert ridc.footprint_bytes(dict(base, order=3, pairs=["ark4", "ark4", "ark4"])) > 0
+    assert ridc.footprint_bytes(dict(base, order=4, pairs=["ark4"] * 4)) == 0    # order 16
+    p = ridc.make_problem(base)
+    e = ridc.make_ext(base)
+    out = ctypes.c_void_p()
+    assert lib.ridc_create_ext(ctypes.byref(p), None, None, ctypes.byref(out)) == \
+        ridc.RIDC_E_INVAL
+    e.reserved = 1
+    assert lib.ridc_create_ext(ctypes.byref(p), ctypes.byref(e), None, ctypes.byref(out)) == \
+        ridc.RIDC_E_INVAL

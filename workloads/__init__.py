@@ -35,6 +35,7 @@ __all__ = [
     "fourier_modes_1d",
     "config_advdiff_1d",
     "config_reacdiff_1d",
+    "config_stiff_1d",
     "config_reacdiff_2d",
     "config_batched_1d",
     "serving_requests",
@@ -123,6 +124,20 @@ def config_reacdiff_1d(n: int = 8192, nt: int = 2000, order: int = 4, T: float =
     """u_t = nu u_xx + u(1-u), Dirichlet 0 on [0, 1], u0 = 8 seeded Gaussians."""
     prob = dict(dim=1, bc="dirichlet", n=n, length=1.0, fe="logistic", a=0.0, nu=nu,
                 T=T, nt=nt, order=order)
+    return prob, bumps_1d(n, seed)
+
+
+def config_stiff_1d(n: int = 8192, nt: int = 400, order: int = 4, T: float = 0.2,
+                    nu: float = 1e-3, kappa: float = 1e3, fi: str = "cubic", fe: str = "none",
+                    pairs=None, seed: int = SEED_BASE + 2):
+    """u_t = nu u_xx + kappa g(u) + f_E(u), Dirichlet 0 on [0, 1], with the reaction g
+    (``cubic``: u - u^3, ``logistic``: u(1-u)) in the stiff part, solved implicitly by Newton's
+    method; u0 = the 8 seeded Gaussians of ``config_reacdiff_1d``.  ``pairs`` (optional): the
+    IMEX pair of each level."""
+    prob = dict(dim=1, bc="dirichlet", n=n, length=1.0, fe=fe, a=0.0, nu=nu, T=T, nt=nt,
+                order=order, fi=fi, kappa=kappa)
+    if pairs is not None:
+        prob["pairs"] = list(pairs)
     return prob, bumps_1d(n, seed)
 
 
