@@ -90,7 +90,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="reacdiff2d",
                     choices=["reacdiff1d", "advdiff1d", "reacdiff2d", "batched1d", "serving",
-                             "paper_advdiff", "paper_burgers"])
+                             "paper_advdiff", "paper_burgers", "stiff1d", "ark1d",
+                             "order_sweep"])
     ap.add_argument("--rate", type=float, default=200.0,
                     help="serving: Poisson arrival rate in requests/s (the configured load is 200)")
     ap.add_argument("--horizon", type=float, default=60.0,
@@ -277,6 +278,132 @@ def bench_1d(args, torch, ridc, which):
                         "pipeline_steps": nt + segments * (P * (P - 1) // 2),
                         "tile": {"threads": tile[0], "rows": tile[1], "flags": tile[2]}},
                 roofline=roof, cpu=cpu, check={"rel_l2_vs_oracle": rel})
+
+
+def imex_delays(pairs):
+    """Pipeline start of each IMEX level: d_0 = 0, d_j = d_{j-1} + S_j - 1 with S_j the order
+    p_0 + .. + p_j of level j (the library's schedule for ARK-based RIDC)."""
+    order = {"fbe": 1, "ark3": 3, "ark4": 4}
+    S, acc, d = [], 0, [0]
+    for x in pairs:
+        acc += order[x]
+        S.append(acc)
+    for j in range(1, len(S)):
+        d.append(d[-1] + S[j] - 1)
+    return S, d
+
+
+def bench_imex(args, torch, ridc, which):
+    """1D IMEX levels: ``stiff1d`` (RIDC4-FBE with the cubic reaction in the stiff part, Newton
+    per stage) and ``ark1d`` (an ARK3 predictor and a forward-backward Euler corrector, order 4,
+    on the N = 8192 reaction-diffusion workload)."""
+    import workloads
+    if which == "stiff1d":
+        prob, u0 = workloads.config_stiff_1d()
+        desc = ("1D u_t = 1e-3 u_xx + 1e3 (u - u^3), Dirichlet [0,1], N=8192, the reaction in "
+                "the stiff part (Newton per stage), 8 seeded Gaussians, RIDC-FBE order 4, "
+                "T=0.2, Nt=400, FP64")
+    else:
+        prob, u0 = workloads.config_reacdiff_1d()
+        prob = dict(prob, order=2, pairs=["ark3", "fbe"])
+        desc = ("1D reaction-diffusion u_t = 1e-3 u_xx + u(1-u), Dirichlet [0,1], N=8192, 8 "
+                "seeded Gaussians, ARK-based RIDC: ARK3 predictor + FBE corrector (order 4), "
+                "T=1, Nt=2000, FP64")
+    if args.nt:
+        prob = dict(prob, nt=args.nt, T=prob["T"] * args.nt / prob["nt"])
+    pairs = prob.get("pairs", ["fbe"] * prob["order"])
+    S, d = imex_delays(pairs)
+    steps, warmup = args.steps or 10, args.warmup if args.warmup is not None else 2
+    n, nt, P = prob["n"], prob["nt"], prob["order"]
+    el, out, s, x0, _ = run_single(args, torch, ridc, prob, u0, "fp64", steps, warmup,
+                                   tune=False)
+    s.begin(x0, nt)
+    if d[-1] > 0:
+        ridc.advance([s], d[-1])              # next step has every level active
+    us, alg = s.kernel_time(args.reps)
+    s.sync()
+    s.close()
+    ach = alg / (us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_imex1d",
+            "launch_us": round(us, 3), "bytes_per_launch": alg,
+            "note": "one workgroup per level; a level reads its value and its window's values "
+                    "and stored f, and writes its value and f; latency-bound (stage solves and "
+                    "Newton iterates inside one workgroup)"}
+    cpu = rel = None
+    if not args.no_cpu:
+        from oracle import Problem, rel_l2
+        from oracle import ridc_ext as X
+        ref, reps, sec = oracle_time(lambda: X.ridc_ark_pipelined(Problem.from_dict(prob), u0,
+                                                                  nt, pairs)[-1])
+        rel = rel_l2(out, ref)
+        cpu = {"value": round(n * nt * reps / sec, 1), "unit": "grid-point-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"the full workload {reps}x (N={n}, Nt={nt}, pairs {pairs}), "
+                         f"{sec:.2f} s, one thread; host has {os.cpu_count()} logical CPUs"}
+    return dict(value=n * nt / el, ms=1e3 * el, steps=steps, warmup=warmup, dtype="f64",
+                config={"workload": desc, "n": n, "nt": nt, "levels": P, "pairs": pairs,
+                        "order": S[-1], "pipeline_steps": nt + d[-1]},
+                roofline=roof, cpu=cpu, check={"rel_l2_vs_oracle": rel})
+
+
+def bench_order_sweep(args, torch, ridc):
+    """Order against wall clock on one GPU (the paper's claim, section IV: a fourth-order RIDC
+    solution in about the wall clock of a first-order one, and more accuracy per second than
+    ARK4): whole integrations of the 1D N = 8192 reaction-diffusion workload (Nt = 2000) and
+    of the 2D 1024^2 one (Nt = 100) for each scheme; the error is against an FP64 RIDC4 run
+    with 4x the steps.  The value is the RIDC4 1D rate."""
+    import workloads
+    steps, warmup = args.steps or 5, args.warmup if args.warmup is not None else 1
+    rows = []
+
+    def timed(prob, u0, prec="fp64"):
+        s = ridc.Ridc(prob, prec=prec)
+        x0 = torch.tensor(np.asarray(u0).reshape(-1), dtype=torch.float64, device="cuda")
+        uT = torch.empty_like(x0)
+        for _ in range(warmup):
+            s.integrate(x0, prob["nt"], uT, sync=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.integrate(x0, prob["nt"], uT, sync=False)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        s.sync()
+        s.close()
+        return el, uT.cpu().numpy()
+
+    base1, v1 = workloads.config_reacdiff_1d()
+    fine = dict(base1, nt=4 * base1["nt"])
+    _, ref1 = timed(fine, v1)
+    schemes1 = [("FBE (order 1)", dict(base1, order=1)),
+                ("RIDC2-FBE", dict(base1, order=2)),
+                ("RIDC3-FBE", dict(base1, order=3)),
+                ("RIDC4-FBE", dict(base1, order=4)),
+                ("ARK3 alone", dict(base1, order=1, pairs=["ark3"])),
+                ("ARK4 alone", dict(base1, order=1, pairs=["ark4"])),
+                ("RIDC: ARK3 + FBE (order 4)", dict(base1, order=2, pairs=["ark3", "fbe"])),
+                ("RIDC: ARK4 + ARK3 (order 7)", dict(base1, order=2, pairs=["ark4", "ark3"]))]
+    value = None
+    for name, prob in schemes1:
+        el, out = timed(prob, v1)
+        err = float(np.linalg.norm(out - ref1) / np.linalg.norm(ref1))
+        rows.append({"grid": "1D N=8192, Nt=2000", "scheme": name, "ms": round(1e3 * el, 3),
+                     "rel_l2_vs_ridc4_4x_steps": err})
+        if name == "RIDC4-FBE":
+            value = base1["n"] * base1["nt"] / el
+    base2, v2 = workloads.config_reacdiff_2d(nt=100, T=0.2)
+    _, ref2 = timed(dict(base2, nt=400), v2)
+    for name, order in (("FBE (order 1)", 1), ("RIDC2-FBE", 2), ("RIDC4-FBE", 4)):
+        el, out = timed(dict(base2, order=order), v2)
+        err = float(np.linalg.norm(out - ref2.reshape(out.shape)) / np.linalg.norm(ref2))
+        rows.append({"grid": "2D 1024^2, Nt=100, T=0.2, FP64", "scheme": name,
+                     "ms": round(1e3 * el, 3), "rel_l2_vs_ridc4_4x_steps": err})
+    desc = ("order against wall clock: 1D reaction-diffusion N=8192 (Nt=2000, T=1) and 2D "
+            "1024^2 (Nt=100, T=0.2), FBE, RIDC2-4, ARK3, ARK4 and ARK-based RIDC, FP64; value = "
+            "RIDC4-FBE 1D rate")
+    return dict(value=value, ms=None, steps=steps, warmup=warmup, dtype="f64",
+                config={"workload": desc, "sweep": rows}, roofline=None, cpu=None, check={})
 
 
 def stencil_roofline(ridc, s, x0, nt, reps):
@@ -534,6 +661,10 @@ def run_workload(args, torch, ridc):
         r = bench_2d(args, torch, ridc)
     elif args.workload == "serving":
         r = bench_serving(args, torch, ridc)
+    elif args.workload in ("stiff1d", "ark1d"):
+        r = bench_imex(args, torch, ridc, args.workload)
+    elif args.workload == "order_sweep":
+        r = bench_order_sweep(args, torch, ridc)
     else:
         r = bench_batched(args, torch, ridc)
     cfg = dict(r["config"], parallelism="single GPU")
@@ -544,7 +675,7 @@ def run_workload(args, torch, ridc):
         "n_gpus": 1,
         "steps": r["steps"],
         "warmup": r["warmup"],
-        "ms_per_step": round(r["ms"], 4),
+        "ms_per_step": round(r["ms"], 4) if r["ms"] is not None else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

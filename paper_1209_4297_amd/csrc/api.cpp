@@ -854,7 +854,7 @@ int validate_ext(const ridc_problem* p, const ridc_ext* e, ImexPlan* out) {
     if (j + 1 < P) pl.frings += vec * pl.R[j];
     if (j > 0)
       pl.weights += sizeof(double) * (size_t)(pl.S[j] - 1) * pl.pair[j].s * 2 * pl.S[j];
-    pl.work += vec * 2 * pl.pair[j].s;
+    pl.work += vec * (2 * pl.pair[j].s + 1);
   }
   pl.rings = align256(pl.rings);
   pl.frings = align256(pl.frings);
@@ -1180,7 +1180,7 @@ int ridc_create_ext(const ridc_problem* p, const ridc_ext* e, void* hip_stream,
     L.prevF = j > 0 ? h->ringF[j - 1] : nullptr;
     L.wt = j > 0 ? wp + woff[j] : nullptr;
     L.ks = kp;
-    kp += (int64_t)2 * pr.s * n;
+    kp += (int64_t)(2 * pr.s + 1) * n;
     L.nt = 0;
     L.sigma0 = 0;
     L.delay = h->delay[j];

@@ -134,17 +134,34 @@ __device__ __forceinline__ double ld(const double* __restrict__ v, int g, int n)
   return 0.0;
 }
 
-// Rows g0-1 .. g0+M of a global vector.
+// Rows g0-1 .. g0+M of a global vector (blocks away from both ends: plain loads).
 template <int M, bool PER>
 __device__ __forceinline__ void load_halo(const Ctx& c, const double* __restrict__ v,
                                           double (&out)[M + 2]) {
+  if (c.g0 >= 1 && c.g0 + M < c.n) {
+    const double* p = v + c.g0 - 1;
+#pragma unroll
+    for (int i = 0; i < M + 2; ++i) out[i] = p[i];
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < M + 2; ++i) out[i] = ld<PER>(v, c.g0 + i - 1, c.n);
 }
 
+// Rows g0 .. g0+M-1: 16-byte loads when the block is inside the grid and 16-byte aligned.
 template <int M>
 __device__ __forceinline__ void load_rows(const Ctx& c, const double* __restrict__ v,
                                           double (&out)[M]) {
+  if (c.g0 + M <= c.n && (reinterpret_cast<uintptr_t>(v + c.g0) & 15) == 0) {
+    const double2* p = reinterpret_cast<const double2*>(v + c.g0);
+#pragma unroll
+    for (int i = 0; i < M / 2; ++i) {
+      const double2 q = p[i];
+      out[2 * i] = q.x;
+      out[2 * i + 1] = q.y;
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < M; ++i) out[i] = c.g0 + i < c.n ? v[c.g0 + i] : 0.0;
 }
@@ -152,6 +169,12 @@ __device__ __forceinline__ void load_rows(const Ctx& c, const double* __restrict
 template <int M>
 __device__ __forceinline__ void store_rows(const Ctx& c, double* __restrict__ v,
                                            const double (&x)[M]) {
+  if (c.g0 + M <= c.n && (reinterpret_cast<uintptr_t>(v + c.g0) & 15) == 0) {
+    double2* p = reinterpret_cast<double2*>(v + c.g0);
+#pragma unroll
+    for (int i = 0; i < M / 2; ++i) p[i] = make_double2(x[2 * i], x[2 * i + 1]);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < M; ++i)
     if (c.g0 + i < c.n) v[c.g0 + i] = x[i];
@@ -310,26 +333,25 @@ __device__ __forceinline__ void tri_solve(Ctx& c, double r, double d0, Rows rows
       for (int k = 0; k < NR; ++k) rd[k][h] = (rd[k][h] - a * dm[k] - cc * dp[k]) * inv;
     }
   }
-  // back substitution
-  double X[NR][M];
+  // back substitution, in place
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
-    X[q][0] = rd[q][0];
-    X[q][M - 1] = rd[q][1];
 #pragma unroll
-    for (int i = 1; i < M - 1; ++i) X[q][i] = D[q][i] - A[i] * rd[q][0] - C[i] * rd[q][1];
+    for (int i = 1; i < M - 1; ++i) D[q][i] = D[q][i] - A[i] * rd[q][0] - C[i] * rd[q][1];
+    D[q][0] = rd[q][0];
+    D[q][M - 1] = rd[q][1];
   }
   if (PER) {
     // x = y - z (v.y) / (1 + v.z),  v = (1, 0, .., 0, r/d0)
     double xl[NR], xr[NR], w0[NR], wn[NR];
-    exchange<M, NR>(c, X, xl, xr, w0, wn);
+    exchange<M, NR>(c, D, xl, xr, w0, wn);
     const double v1 = r / d0;
     const double f = (w0[0] + v1 * wn[0]) / (1.0 + w0[NR - 1] + v1 * wn[NR - 1]);
 #pragma unroll
-    for (int i = 0; i < M; ++i) x[i] = X[0][i] - f * X[NR - 1][i];
+    for (int i = 0; i < M; ++i) x[i] = D[0][i] - f * D[NR - 1][i];
   } else {
 #pragma unroll
-    for (int i = 0; i < M; ++i) x[i] = X[0][i];
+    for (int i = 0; i < M; ++i) x[i] = D[0][i];
   }
 }
 
@@ -350,16 +372,33 @@ __device__ __forceinline__ Edges<M> edges(Ctx& c, const double (&x)[M]) {
 }
 
 // Solve y - tau f^S(y) = rhs for this thread's rows (guess in y on entry).  Linear f^S: one
-// solve.  Otherwise Newton's method with the stopping rule: the largest update is below
-// 1e-15 max(1, max|y|), or below 1e-11 max(1, max|y|) and above half the previous one
-// (rounding noise); after maxit iterates without stopping, y becomes NaN.
-template <int M, bool PER>
+// solve and one step of iterative refinement with the FP64 residual, so that each stage is the
+// exact solution of its linear system to rounding (section II).  Otherwise Newton's method
+// with the stopping rule: the largest update is below 1e-15 max(1, max|y|), or below
+// 1e-11 max(1, max|y|) and above half the previous one (rounding noise); after maxit iterates
+// without stopping, y becomes NaN.  MEM: the right-hand side is read from rhs_mem (rows g0..)
+// instead of registers, which keeps the largest blocks (16 rows per thread) out of scratch.
+template <int M, bool PER, bool MEM>
 __device__ __forceinline__ void stage_solve(Ctx& c, double tau, int maxit, const double (&rhs)[M],
-                                            double (&y)[M]) {
+                                            const double* __restrict__ rhs_mem, double (&y)[M]) {
   const double r = tau * c.nu_h2;
   const double b0 = 1.0 + 2.0 * r;
+  auto rhs_at = [&](int i) { return MEM ? rhs_mem[c.g0 + i] : rhs[i]; };
   if (c.fs == RIDC_FS_DIFFUSION) {
-    tri_solve<M, PER>(c, r, b0, [&](int i, double& b, double& d) { b = b0; d = rhs[i]; }, y);
+    tri_solve<M, PER>(c, r, b0, [&](int i, double& b, double& d) { b = b0; d = rhs_at(i); }, y);
+    const Edges<M> e = edges<M, PER>(c, y);
+    double delta[M];
+    tri_solve<M, PER>(
+        c, r, b0,
+        [&](int i, double& b, double& d) {
+          double um, up;
+          nbrs<M, PER>(c, y, i, e.l, e.r, e.w0, e.wn, um, up);
+          d = rhs_at(i) - (y[i] - tau * c.nu_h2 * (up - 2.0 * y[i] + um));
+          b = b0;
+        },
+        delta);
+#pragma unroll
+    for (int i = 0; i < M; ++i) y[i] += delta[i];
     return;
   }
   double last = __builtin_inf();
@@ -372,7 +411,7 @@ __device__ __forceinline__ void stage_solve(Ctx& c, double tau, int maxit, const
         [&](int i, double& b, double& d) {
           double um, up;
           nbrs<M, PER>(c, y, i, e.l, e.r, e.w0, e.wn, um, up);
-          d = rhs[i] - (y[i] - tau * fstiff(c, um, y[i], up));
+          d = rhs_at(i) - (y[i] - tau * fstiff(c, um, y[i], up));
           b = b0 - tau * c.kappa * react_prime(c.fs, y[i]);
         },
         delta);
@@ -492,17 +531,18 @@ __device__ void imex_step(const ImexLvl& L, int64_t sigma, bool init, double* ld
       for (int x = 0; x < M; ++x) rhs[x] = rhs[x] + (as * kS[x] + an * kN[x]);
     }
     const double a = L.AS[i][i];
-    double fs[M], um_up[2][M];
+    double kS[M];   // f^S(Y_i), then K^S_i
+    Edges<M> e;     // neighbours of this thread's block of Y_i
     if (a == 0.0) {
-      // stage 0 (c_0 = 0): Y_0 = y_n, neighbours from memory
-      double u[M + 2];
-      load_halo<M, PER>(c, yn_p, u);
+      // stage 0 (c_0 = 0): Y_0 = y_n
+#pragma unroll
+      for (int x = 0; x < M; ++x) Y[x] = rhs[x];
+      e = edges<M, PER>(c, Y);
 #pragma unroll
       for (int x = 0; x < M; ++x) {
-        Y[x] = rhs[x];
-        um_up[0][x] = u[x];
-        um_up[1][x] = u[x + 2];
-        fs[x] = fstiff(c, u[x], Y[x], u[x + 2]);
+        double um, up;
+        nbrs<M, PER>(c, Y, x, e.l, e.r, e.w0, e.wn, um, up);
+        kS[x] = fstiff(c, um, Y[x], up);
       }
     } else {
       const double tau = dt * a;
@@ -514,16 +554,17 @@ __device__ void imex_step(const ImexLvl& L, int64_t sigma, bool init, double* ld
       }
 #pragma unroll
       for (int x = 0; x < M; ++x) Y[x] = guess[x];
-      stage_solve<M, PER>(c, tau, L.maxit, rhs, Y);
-      const Edges<M> e = edges<M, PER>(c, Y);
+      constexpr bool kMem = M >= 16;
+      double* rhs_p = sn_p + n;                             // third scratch vector
+      if (kMem) store_rows<M>(c, rhs_p, rhs);
+      stage_solve<M, PER, kMem>(c, tau, L.maxit, rhs, rhs_p, Y);
+      if (kMem) load_rows<M>(c, rhs_p, rhs);
+      e = edges<M, PER>(c, Y);
 #pragma unroll
-      for (int x = 0; x < M; ++x) {
-        nbrs<M, PER>(c, Y, x, e.l, e.r, e.w0, e.wn, um_up[0][x], um_up[1][x]);
-        fs[x] = (Y[x] - rhs[x]) / tau;
-      }
+      for (int x = 0; x < M; ++x) kS[x] = (Y[x] - rhs[x]) / tau;
     }
     if (i < s - 1) {
-      double kS[M], kN[M], ssv[M], snv[M];
+      double kN[M], ssv[M], snv[M];
       if (corr) {
         load_rows<M>(c, ss_p, ssv);
         load_rows<M>(c, sn_p, snv);
@@ -533,8 +574,10 @@ __device__ void imex_step(const ImexLvl& L, int64_t sigma, bool init, double* ld
       }
 #pragma unroll
       for (int x = 0; x < M; ++x) {
-        kS[x] = fs[x] - ssv[x];
-        kN[x] = fe_eval(c.fe, c.ce, um_up[0][x], Y[x], um_up[1][x]) - snv[x];
+        double um, up;
+        nbrs<M, PER>(c, Y, x, e.l, e.r, e.w0, e.wn, um, up);
+        kS[x] = kS[x] - ssv[x];
+        kN[x] = fe_eval(c.fe, c.ce, um, Y[x], up) - snv[x];
       }
       store_rows<M>(c, L.ks + (int64_t)(2 * i) * n, kS);
       store_rows<M>(c, L.ks + (int64_t)(2 * i + 1) * n, kN);
@@ -544,9 +587,11 @@ __device__ void imex_step(const ImexLvl& L, int64_t sigma, bool init, double* ld
       if (L.ownF) {
         double f[M];
 #pragma unroll
-        for (int x = 0; x < M; ++x)
-          f[x] = fstiff(c, um_up[0][x], Y[x], um_up[1][x]) +
-                 fe_eval(c.fe, c.ce, um_up[0][x], Y[x], um_up[1][x]);
+        for (int x = 0; x < M; ++x) {
+          double um, up;
+          nbrs<M, PER>(c, Y, x, e.l, e.r, e.w0, e.wn, um, up);
+          f[x] = fstiff(c, um, Y[x], up) + fe_eval(c.fe, c.ce, um, Y[x], up);
+        }
         store_rows<M>(c, L.ownF + slot, f);
       }
     }
@@ -591,6 +636,9 @@ hipError_t launch_m(int M, const ImexLvl* items, int count, int threads, int64_t
 }  // namespace
 
 void imex_shape(int64_t n, int* M, int* threads) {
+  // the fewest rows per thread that keep the workgroup within 512 threads (measured: longer
+  // per-thread blocks with fewer waves are slower at every size, the elimination chain and the
+  // register pressure outweighing the PCR stages saved)
   int m = 2;
   while (m < kImexMaxRows && (n + m - 1) / m > kImexMaxThreads) m *= 2;
   const int64_t t = (n + m - 1) / m;

@@ -186,7 +186,7 @@ struct ImexLvl {
   const double* prev;     // previous level's values (R_prev slots); null for the predictor
   const double* prevF;    // previous level's f
   const double* wt;       // corrector weights: [row r = 0..S-2][stage i][interp S, quad S]
-  double* ks;             // stage workspace: K^S_l, K^N_l (l < s-1), then 2 scratch vectors
+  double* ks;             // stage workspace: K^S_l, K^N_l (l < s-1), then 3 scratch vectors
   int64_t nt, sigma0, delay;
   int32_t n, j, s, S;     // unknowns, level, stages of the pair, window nodes (corrector)
   int32_t R_own, R_prev;

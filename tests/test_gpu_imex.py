@@ -174,3 +174,15 @@ def test_grouped_imex_launches_are_bitwise_solo(env):
     ref = X.ridc_ark_pipelined(Problem.from_dict(cases[0][0]), cases[0][1], 30,
                                ["ark3", "fbe"])[-1]
     assert rel_l2(solo[0], ref) <= TOL
+
+
+@pytest.mark.parametrize("which", ["ark3-fbe N=8192 Nt=2000", "stiff N=8192 Nt=400"])
+def test_full_length_workloads(env, which):
+    # the two benchmarked IMEX workloads at their full length: rounding must not accumulate
+    # past the bar (each linear stage is refined once, each Newton stage solved to rounding)
+    if which.startswith("ark3"):
+        prob, u0 = workloads.config_reacdiff_1d()
+        prob = dict(prob, order=2, pairs=["ark3", "fbe"])
+    else:
+        prob, u0 = workloads.config_stiff_1d()
+    check(env, prob, u0, prob["nt"])
