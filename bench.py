@@ -156,8 +156,8 @@ def run_single(args, torch, ridc, prob, u0, prec, steps, warmup, tune=True, segm
         tile = tuple(int(x) for x in args.tile.split(",")) + (0,)
         tile = tile[:3]
         s.set_tile(*tile)
-    elif tune and prob["dim"] == 1:
-        tile = s.autotune()
+    elif tune:
+        tile = s.autotune()     # 1D tiling, or the 2D transform-pass shape (cached per n, prec)
     x0 = torch.tensor(np.asarray(u0).reshape(-1), dtype=torch.float64, device="cuda")
     uT = torch.empty_like(x0)
     def run():
@@ -406,6 +406,15 @@ def bench_order_sweep(args, torch, ridc):
                 config={"workload": desc, "sweep": rows}, roofline=None, cpu=None, check={})
 
 
+def shape_name(shape):
+    """The 2D transform-pass shape ridc_autotune chose: (threads, 0, shape bits)."""
+    if shape is None:
+        return None
+    bits = shape[2]
+    return {"threads": shape[0], "wave_columns": 64 if bits & 1 else 32,
+            "k_slice": "32 (two LDS stages)" if bits & 2 else "default"}
+
+
 def stencil_roofline(ridc, s, x0, nt, reps):
     """HBM roofline of the right-hand-side kernel (stencils and quadrature of every level) at a
     steady-state step of the same integration."""
@@ -433,8 +442,9 @@ def bench_2d(args, torch, ridc):
     n, nt, P = prob["n"], prob["nt"], prob["order"]
     steps, warmup = args.steps or 3, args.warmup if args.warmup is not None else 1
     reps = max(10, args.reps // 10)
-    el, out, s, x0, _ = run_single(args, torch, ridc, prob, u0, args.prec, steps, warmup)
+    el, out, s, x0, shape = run_single(args, torch, ridc, prob, u0, args.prec, steps, warmup)
     roof = roofline_single(ridc, s, x0, nt, reps, "mfma", args.prec)
+    roof["pass_shape"] = shape_name(shape)
     roof_rhs = stencil_roofline(ridc, s, x0, nt, reps)
     if args.nt is None:
         roof["traffic"] = measured_traffic("reacdiff2d", args.prec)
@@ -469,9 +479,10 @@ def bench_2d(args, torch, ridc):
             check["matched"] = bool(check["rel_l2_vs_fp64_gpu"] <= 0.1 * err_disc)
         if not args.no_matched and args.prec == "fp64":
             for prec in ("bf16x3", "fp32"):
-                el_m, out_m, sm, _, _ = run_single(args, torch, ridc, prob, u0, prec, steps,
-                                                   warmup)
+                el_m, out_m, sm, _, shape_m = run_single(args, torch, ridc, prob, u0, prec,
+                                                         steps, warmup)
                 roof_m = roofline_single(ridc, sm, x0, nt, reps, "mfma", prec)
+                roof_m["pass_shape"] = shape_name(shape_m)
                 sm.close()
                 dist = float(np.linalg.norm(out_m - u64) / np.linalg.norm(u64))
                 matched[prec] = {
@@ -484,7 +495,7 @@ def bench_2d(args, torch, ridc):
                     "matched": bool(dist <= 0.1 * err_disc),
                     "roofline": {k: roof_m[k] for k in ("bound", "achieved", "peak", "unit",
                                                         "frac", "kernel", "launch_us",
-                                                        "flops_per_launch")}}
+                                                        "flops_per_launch", "pass_shape")}}
     cpu = None
     if not args.no_cpu:
         from oracle import Problem, ridc_pipelined

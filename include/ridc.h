@@ -235,16 +235,28 @@ int ridc_pcr_plan(double r, int64_t m, int32_t* stages, double* divisor);
 int ridc_step_cost(const ridc_handle* h, double* hbm_bytes, double* flops);
 
 /* ---- tuning --------------------------------------------------------------------------------- */
-/* Measure candidate 1D tilings (threads per workgroup; whole cycle per workgroup, or chunks of
- * `rows` rows with a PCR halo) on the handle's stream and keep the fastest for this handle and
- * for later handles with the same (n, boundary, PCR stages).  Every tiling performs the same
+/* Choose the handle's launch shape by measurement and record it in the tuning table (see
+ * ridc_tune_save) for later handles with the same key:
+ *  - 1D: candidate tilings (threads per workgroup; whole cycle per workgroup, or chunks of
+ *    `rows` rows with a PCR halo; the whole-range workgroup), keyed by (n, boundary, PCR
+ *    stages).  threads_out/rows_out/flags_out (nullable) receive the choice (rows 0 = whole
+ *    cycle; flags as in ridc_set_tile).
+ *  - 2D: the transform-pass shapes the handle's side and precision allow, keyed by (n,
+ *    precision): 32- or 64-column waves (FP32/FP64 passes), 64- or 32-wide k-slices
+ *    (split-BF16 pass), each timed over 20 launches of a pass.  threads_out receives the
+ *    threads per block, rows_out 0, flags_out the shape bits (1: 64-column waves, 2: 32-wide
+ *    slices).
+ * A shape already recorded for the key (this process, or the tuning cache file) is applied
+ * without measuring; ridc_tune_clear forgets the table.  Every shape performs the same
  * operations for every output value, so results are bitwise independent of the choice.  The
- * tuning steps overwrite the level rings: the handle must be re-armed (ridc_begin) afterwards.
- * threads_out/rows_out/flags_out (nullable) receive the choice (rows 0 = whole cycle; flags as
- * in ridc_set_tile).  2D: no-op.                                                              */
+ * tuning launches overwrite the level rings: the handle must be re-armed (ridc_begin).
+ * IMEX handles (ridc_create_ext): RIDC_E_UNSUPPORTED.                                        */
 int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out);
 
-/* Force a 1D tiling: threads in {64,128,256,512,1024}; rows = 0 for the whole cycle in one
+/* 2D handles: set the transform-pass shape bits `flags` (1: 64-column waves, FP32/FP64 passes
+ * with n/2 a multiple of 64 or no fold; 2: 32-wide k-slices, split-BF16 pass; 0: the default);
+ * rows must be 0 and threads is ignored; results do not depend on the shape.
+ * 1D: force a tiling: threads in {64,128,256,512,1024}; rows = 0 for the whole cycle in one
  * workgroup, else chunks of `rows` rows (allowed when the PCR coupling vanishes within a halo
  * shorter than the system); flags bit 0 = write level values with nontemporal stores; flags
  * bit 1 = one workgroup of `threads` (512 or 1024, rows 0) runs every level and many pipeline
@@ -265,11 +277,26 @@ int ridc_set_batch_tile(int32_t threads, int32_t rows);
 
 /* Time one grouped launch of the 1D handles among hs[0..count) for every candidate batch tiling
  * (threads x rows, 20 steady-state steps each, HIP events on the first 1D handle's stream) and
- * set the fastest as with ridc_set_batch_tile.  The timed steps overwrite the level rings, so
- * every 1D handle is left unarmed (call ridc_begin again).  threads_out and rows_out (nullable)
- * receive the choice.  Errors: RIDC_E_INVAL for bad handles, RIDC_E_HIP on launch failures.   */
+ * set the fastest as with ridc_set_batch_tile, recording it in the tuning table; a grouped
+ * tiling already recorded there (this process or the cache file) is set without measuring.
+ * The timed steps overwrite the level rings, so every 1D handle is left unarmed (call
+ * ridc_begin again).  threads_out and rows_out (nullable) receive the choice.  Errors:
+ * RIDC_E_INVAL for bad handles, RIDC_E_HIP on launch failures.                               */
 int ridc_autotune_batch(ridc_handle* const* hs, int32_t count, int32_t* threads_out,
                         int32_t* rows_out);
+
+/* Tuning table.  The autotuners record their choices in a process-wide table, loaded on first
+ * use from a JSON file and rewritten after every new entry: $RIDC_TUNE_CACHE if set (empty or
+ * "off": no file), else $XDG_CACHE_HOME/ridc/tune.json, else $HOME/.cache/ridc/tune.json.  The
+ * file names the GPU it was measured on (architecture and compute units); entries of another
+ * GPU are not loaded.  A cache that cannot be written is not an error.
+ * ridc_tune_save: write the table to `path` (NULL = the default file).
+ * ridc_tune_load: merge the entries of `path` (NULL = the default file) into the table.
+ * ridc_tune_clear: forget every entry in memory (the file is kept; it is not reloaded).
+ * Errors: RIDC_E_INVAL when the file cannot be written or read.                               */
+int ridc_tune_save(const char* path);
+int ridc_tune_load(const char* path);
+int ridc_tune_clear(void);
 
 /* Average duration of the dominant kernel per pipeline step, from HIP events on the handle's
  * stream, starting at the handle's next pipeline step (which must have every level active):

@@ -157,29 +157,44 @@ struct Tile1D {
 };
 
 std::mutex g_tune_mu;
-struct TuneKey {
-  int64_t n;
-  int bc;
-  int stages;
-};
-std::vector<std::pair<TuneKey, Tile1D>> g_tuned;
 
 // Tiling of grouped 1D launches (process-wide, guarded by g_tune_mu): threads per workgroup and
-// the most LDS rows one workgroup holds (0: whole cycles whenever they fit).
+// the most LDS rows one workgroup holds (0: whole cycles whenever they fit).  Until it is set or
+// measured, a tiling recorded in the tuning cache applies.
 struct BatchTile {
   int threads = 256;
   int rows = 0;
 };
 BatchTile g_batch_tile;
+bool g_batch_tile_set = false;
 
-bool tuned_tile(int64_t n, int bc, int stages, Tile1D* t) {
+BatchTile current_batch_tile() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  for (auto& e : g_tuned)
-    if (e.first.n == n && e.first.bc == bc && e.first.stages == stages) {
-      *t = e.second;
-      return true;
-    }
-  return false;
+  if (!g_batch_tile_set) {
+    int t = 0, r = 0;
+    if (tune_get_batch(&t, &r)) g_batch_tile = BatchTile{t, r};
+    g_batch_tile_set = true;
+  }
+  return g_batch_tile;
+}
+
+// ridc_set_tile's (threads, rows, flags) as a tiling, and back
+Tile1D tile_from(int threads, int rows, int flags) {
+  if (flags & 2) return Tile1D{1, 0, 256, 0, threads};
+  return Tile1D{rows == 0 ? 1 : 0, rows, threads, flags & 1, 0};
+}
+void tile_to(const Tile1D& t, int* threads, int* rows, int* flags) {
+  *threads = t.fused ? t.fused : t.threads;
+  *rows = t.wrap ? 0 : t.B;
+  *flags = t.nt_store | (t.fused ? 2 : 0);
+}
+
+// the measured tiling of this system, if the tuning table has one
+bool tuned_tile(int64_t n, int bc, int stages, Tile1D* t) {
+  int th = 0, r = 0, f = 0;
+  if (!tune_get_1d(n, bc, stages, &th, &r, &f)) return false;
+  *t = tile_from(th, r, f);
+  return true;
 }
 
 int64_t halo_rows(const PcrPlan& pcr) {
@@ -917,6 +932,56 @@ int advance_imex(const std::vector<ridc_handle*>& hs, int64_t max_steps, hipStre
   return RIDC_OK;
 }
 
+// 2D: the transform-pass shape of the handle's (n, precision), from the tuning table or
+// measured: every shape the plan allows times `reps` launches of the first pass of a step with
+// every level active (on zeroed rings), the fastest is kept and recorded.  Leaves the handle
+// unarmed.  Outputs: threads per block of the chosen shape, 0, and the shape bits.
+int autotune_2d(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out) {
+  Plan2D* pl = h->p2;
+  const int prec = h->p.prec;
+  int tile = 0;
+  if (!tune_get_2d(h->p.n, prec, &tile) || plan2d_set_tile(pl, tile) != RIDC_OK) {
+    std::vector<int> cands;
+    plan2d_tile_candidates(pl, &cands);
+    tile = cands[0];
+    if (cands.size() > 1) {
+      int64_t slots = 0;
+      for (int j = 0; j < h->P; ++j) slots += h->R[j];
+      RIDC_HIP_TRY(hipMemsetAsync(h->ring[0], 0, sizeof(double) * (size_t)(slots * h->npts),
+                                  h->stream));
+      int rc = plan2d_arm(pl, (int64_t)1 << 30, h->stream);
+      if (rc != RIDC_OK) return rc;
+      const int64_t s = (int64_t)h->P * (h->P - 1) / 2 + 1;   // every level active
+      double best = 1e300;
+      for (int c : cands) {
+        rc = plan2d_set_tile(pl, c);
+        if (rc != RIDC_OK) return rc;
+        double us = 0;
+        rc = plan2d_time_pass(pl, s, 20, h->stream, &us);
+        if (rc != RIDC_OK) return rc;
+        if (us < best) {
+          best = us;
+          tile = c;
+        }
+      }
+    }
+    tune_put_2d(h->p.n, prec, tile);
+    int rc = plan2d_set_tile(pl, tile);
+    if (rc != RIDC_OK) return rc;
+  }
+  h->nt = -1;
+  h->sigma = h->total = 0;
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  h->graph_nt = -1;
+  if (threads_out) *threads_out = (tile & kPassWide64) ? 256 : 512;
+  if (rows_out) *rows_out = 0;
+  if (flags_out) *flags_out = tile;
+  return RIDC_OK;
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -1307,11 +1372,7 @@ int ridc_advance(ridc_handle* const* hs, int32_t count, int64_t max_steps) {
     }
   }
   if (!h1.empty()) {
-    BatchTile bt;
-    {
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      bt = g_batch_tile;
-    }
+    const BatchTile bt = current_batch_tile();
     BatchStage st;
     rc = stage_batch_1d(h1, bt, false, stream, &st);
     if (rc != RIDC_OK) return rc;
@@ -1550,7 +1611,19 @@ int ridc_integrate_batch(ridc_handle* const* hs, int32_t count, const double* co
 int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags) {
   if (!h) return fail(RIDC_E_INVAL, "NULL handle");
   if (h->imex) return fail(RIDC_E_UNSUPPORTED, "IMEX levels have one launch shape per n");
-  if (h->p.dim != 1) return fail(RIDC_E_UNSUPPORTED, "tiles are chosen per system in 1D only");
+  if (h->p.dim == 2) {
+    // the transform-pass shape bits; threads and rows are implied by them
+    (void)threads;
+    if (rows != 0) return fail(RIDC_E_INVAL, "2D shapes take rows = 0");
+    int rc = plan2d_set_tile(h->p2, flags);
+    if (rc != RIDC_OK) return rc;
+    if (h->gexec) {
+      (void)hipGraphExecDestroy(h->gexec);
+      h->gexec = nullptr;
+    }
+    h->graph_nt = -1;
+    return RIDC_OK;
+  }
   if (rows < 0 || (flags & ~3)) return fail(RIDC_E_INVAL, "bad rows or flags");
   if (flags & 2) {
     if (rows != 0) return fail(RIDC_E_INVAL, "the whole-range workgroup holds whole cycles");
@@ -1563,11 +1636,20 @@ int ridc_set_tile(ridc_handle* h, int32_t threads, int32_t rows, int32_t flags) 
 int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out) {
   if (!h) return fail(RIDC_E_INVAL, "NULL handle");
   if (h->imex) return fail(RIDC_E_UNSUPPORTED, "IMEX levels have one launch shape per n");
-  if (h->p.dim != 1) {
-    if (threads_out) *threads_out = 512;
-    if (rows_out) *rows_out = 128;
-    if (flags_out) *flags_out = 0;
-    return RIDC_OK;                      // 2D launch shapes are fixed per precision
+  if (h->p.dim != 1) return autotune_2d(h, threads_out, rows_out, flags_out);
+  {
+    // a tiling recorded for this system (this process, or the tuning cache) is taken as is
+    Tile1D t;
+    if (tuned_tile(h->p.n, h->p.bc, h->pcr.stages, &t) && tile_fits(&h->p, h->pcr, t)) {
+      int rc = apply_tile_1d(h, t);
+      if (rc != RIDC_OK) return rc;
+      int th, r, f;
+      tile_to(t, &th, &r, &f);
+      if (threads_out) *threads_out = th;
+      if (rows_out) *rows_out = r;
+      if (flags_out) *flags_out = f;
+      return RIDC_OK;
+    }
   }
   // the tuning steps overwrite the rings: start from zeros, leave the handle unarmed
   int64_t slots = 0;
@@ -1593,23 +1675,34 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32
     }
   }
   if (best_ms >= 1e29f) return fail(RIDC_E_UNSUPPORTED, "no tile fits");
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    bool found = false;
-    for (auto& e : g_tuned)
-      if (e.first.n == h->p.n && e.first.bc == h->p.bc && e.first.stages == h->pcr.stages) {
-        e.second = best;
-        found = true;
-      }
-    if (!found) g_tuned.push_back({TuneKey{h->p.n, h->p.bc, h->pcr.stages}, best});
-  }
+  int th, r, f;
+  tile_to(best, &th, &r, &f);
+  tune_put_1d(h->p.n, h->p.bc, h->pcr.stages, th, r, f);
   h->nt = -1;
   h->sigma = h->total = 0;
   int rc = apply_tile_1d(h, best);
   if (rc != RIDC_OK) return rc;
-  if (threads_out) *threads_out = best.fused ? best.fused : best.threads;
-  if (rows_out) *rows_out = best.wrap ? 0 : best.B;
-  if (flags_out) *flags_out = best.nt_store | (best.fused ? 2 : 0);
+  if (threads_out) *threads_out = th;
+  if (rows_out) *rows_out = r;
+  if (flags_out) *flags_out = f;
+  return RIDC_OK;
+}
+
+int ridc_tune_save(const char* path) { return tune_save(path); }
+
+int ridc_tune_load(const char* path) {
+  int rc = tune_load(path);
+  if (rc != RIDC_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_batch_tile_set = false;             // a loaded grouped tiling applies from the next launch
+  return RIDC_OK;
+}
+
+int ridc_tune_clear(void) {
+  tune_clear();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_batch_tile = BatchTile{};
+  g_batch_tile_set = false;
   return RIDC_OK;
 }
 
@@ -1619,6 +1712,7 @@ int ridc_set_batch_tile(int32_t threads, int32_t rows) {
   if (rows < 0 || (rows > 0 && rows < 256)) return fail(RIDC_E_INVAL, "batch rows: 0 or >= 256");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_batch_tile = BatchTile{threads, rows};
+  g_batch_tile_set = true;
   return RIDC_OK;
 }
 
@@ -1629,10 +1723,18 @@ int ridc_autotune_batch(ridc_handle* const* hs, int32_t count, int32_t* threads_
   std::vector<ridc_handle*> h1;
   for (int32_t i = 0; i < count; ++i)
     if (hs[i]->p.dim == 1 && !hs[i]->imex) h1.push_back(hs[i]);
-  BatchTile best;
+  BatchTile best = current_batch_tile();
   {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    best = g_batch_tile;
+    // a grouped tiling recorded in the tuning table (this process or the cache) is taken as is
+    int t = 0, r = 0;
+    if (tune_get_batch(&t, &r)) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_batch_tile = BatchTile{t, r};
+      g_batch_tile_set = true;
+      if (threads_out) *threads_out = t;
+      if (rows_out) *rows_out = r;
+      return RIDC_OK;
+    }
   }
   if (!h1.empty()) {
     hipStream_t stream = h1[0]->stream;
@@ -1685,8 +1787,12 @@ int ridc_autotune_batch(ridc_handle* const* hs, int32_t count, int32_t* threads_
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (rc != RIDC_OK) return rc;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_batch_tile = best;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_batch_tile = best;
+      g_batch_tile_set = true;
+    }
+    tune_put_batch(best.threads, best.rows);
   }
   if (threads_out) *threads_out = best.threads;
   if (rows_out) *rows_out = best.rows;
@@ -1716,11 +1822,7 @@ int ridc_batch_kernel_time(ridc_handle* const* hs, int32_t count, int32_t reps,
     h1.push_back(h);
   }
   if (h1.empty()) return fail(RIDC_E_INVAL, "no handles");
-  BatchTile bt;
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    bt = g_batch_tile;
-  }
+  const BatchTile bt = current_batch_tile();
   hipStream_t stream = h1[0]->stream;
   BatchStage st;
   rc = stage_batch_1d(h1, bt, false, stream, &st);

@@ -89,6 +89,8 @@ struct Plan2D {
   const u16* Qbf = nullptr;         // hi then lo
   double* lam = nullptr;
   hipStream_t stream = nullptr;
+  int tile = 0;                     // pass launch shape: kPassWide64 | kPassNarrowK (results
+                                    // are bitwise the same for every shape)
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -344,7 +346,13 @@ static void launch_stencil(void (*k)(const Lvl2D*, int64_t), const Lvl2D* lv, in
 //   tiles of 16 x 16; k staged through LDS in slices of BK with 16-byte global loads
 // ---------------------------------------------------------------------------------------------
 constexpr int BT = 128;      // block tile (rows of A x columns of Q)
-constexpr int NTHR = 512;    // threads per block
+// A wave computes 64 rows x WC columns of the block tile: WC = 32 (8 waves of 512 threads, two
+// per SIMD) or WC = 64 (4 waves of 256 threads, one per SIMD with the whole register file,
+// fewer LDS reads per MFMA).
+template <int WC>
+constexpr int pass_threads() {
+  return WC == 64 ? 256 : 512;
+}
 
 template <int PREC>
 struct Tr;
@@ -434,9 +442,12 @@ constexpr size_t pass_lds_bytes(int fold) {
   return (size_t)lds_stages<PREC, KX>() * ((fold ? 2 : 1) * NSPLIT + NSPLIT) * BT * LDE * sizeof(T);
 }
 
-template <int PREC, int OUT, int FOLD, int KX>
-__global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ passes,
-                                                 const Lvl2D* __restrict__ levels, int64_t sigma) {
+template <int PREC, int OUT, int FOLD, int KX, int WC>
+__global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __restrict__ passes,
+                                                               const Lvl2D* __restrict__ levels,
+                                                               int64_t sigma) {
+  constexpr int NTHR = pass_threads<WC>();
+  constexpr int NB = WC / 16;                         // 16-column MFMA tiles per wave
   typedef Tr<PREC> TR;
   typedef typename TR::T T;
   typedef typename TR::Acc Acc;
@@ -497,14 +508,14 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave >> 2) * 64;           // wave tile origin inside the block
-  const int wn = (wave & 3) * 32;
+  const int wm = (wave / (BT / WC)) * 64;    // wave tile origin inside the block
+  const int wn = (wave % (BT / WC)) * WC;
 
-  Acc acc[4][2];
+  Acc acc[4][NB];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+    for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
   // global -> register staging of one k-slice (A, its mirrored columns when folding, Q); a
   // slice's loads are issued one MFMA phase before they are stored into LDS
@@ -613,11 +624,11 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       }
   };
 
-  // the A operand of each 16-column group of this wave: sums (0) for even output columns,
-  // differences (1) for odd ones -- uniform per group since n/2 is a multiple of 32
+  // the A operand of this wave's WC output columns: sums (0) for even output columns,
+  // differences (1) for odd ones -- uniform per wave, since n/2 and the wave's first column are
+  // multiples of WC (the launcher takes WC = 64 only when n/2 is a multiple of 64)
   const int half = n >> 1;
   const int pa0 = FOLD && col0 + wn >= half ? 1 : 0;
-  const int pa1 = FOLD && col0 + wn + 16 >= half ? 1 : 0;
   const int KT = K / BK;
   const int r16 = lane & 15;
   auto mfma_slice = [&](int stage) {
@@ -628,19 +639,13 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
     for (int ks = 0; ks < KX; ++ks) {
       // lane holds 8 consecutive k of row (l % 16), k offset 8 (l / 16), of k-step ks of 32
       const int kb = (lane >> 4) * 16 + ks * 64;       // byte offset of the 8 k values
-      bf16x8 ahi[2][4], alo[2][4], bhi[2], blo[2];
+      static_assert(NB == 2, "the split-BF16 pass takes 32-column waves");
+      bf16x8 ahi[4], alo[4], bhi[2], blo[2];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int ro = (wm + t * 16 + r16) * ROWB + kb;
-        ahi[0][t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa0][0] + ro));
-        alo[0][t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa0][1] + ro));
-        if (pa1 != pa0) {
-          ahi[1][t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa1][0] + ro));
-          alo[1][t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa1][1] + ro));
-        } else {
-          ahi[1][t] = ahi[0][t];
-          alo[1][t] = alo[0][t];
-        }
+        ahi[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa0][0] + ro));
+        alo[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa0][1] + ro));
       }
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
@@ -652,58 +657,92 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[b][a], bhi[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[b][a], blo[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[b][a], bhi[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[a], bhi[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], blo[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], bhi[b], acc[a][b], 0, 0, 0);
         }
     }
-    } else {
-      // k-steps of 4: lane holds element (row l % 16, k 4i + l / 16) of step i; its KQ values
-      // of the slice are contiguous in the permuted rows, read 16 bytes at a time
-      const int k4 = lane >> 4;
-      constexpr int EV = 16 / (int)sizeof(T);
-      struct Frag {
-        T x[KQ];
+    }
+  };
+  // FP32/FP64 k-steps of 4: lane holds element (row l % 16, k 4i + l / 16) of step i; its KQ
+  // values of a slice are contiguous in the permuted rows, read 16 bytes at a time
+  constexpr int EV = 16 / (int)sizeof(T);
+  struct Frag {
+    T x[KQ];
+  };
+  auto frag = [&](const T* row) {
+    Frag f;
+    const int k4 = lane >> 4;
+#pragma unroll
+    for (int v = 0; v < KQ / EV; ++v) {
+      const u32x4 w = *(const u32x4*)(row + k4 * KQ + v * EV);
+      struct Ev {
+        T x[EV];
       };
-      auto frag = [&](const T* row) {
-        Frag f;
+      const Ev ev = __builtin_bit_cast(Ev, w);
 #pragma unroll
-        for (int v = 0; v < KQ / EV; ++v) {
-          const u32x4 w = *(const u32x4*)(row + k4 * KQ + v * EV);
-          struct Ev {
-            T x[EV];
-          };
-          const Ev ev = __builtin_bit_cast(Ev, w);
+      for (int e = 0; e < EV; ++e) f.x[v * EV + e] = ev.x[e];
+    }
+    return f;
+  };
+  // this wave's fragments of the slice in LDS stage `stage`: 4 tiles of A rows, 2 of Q rows
+  auto read_frags = [&](int stage, Frag (&fa)[4], Frag (&fb)[NB]) {
+    T (*As)[NSPLIT][BT * LDE] = stage_a(stage);
+    T (*Bs)[BT * LDE] = stage_b(stage);
 #pragma unroll
-          for (int e = 0; e < EV; ++e) f.x[v * EV + e] = ev.x[e];
-        }
-        return f;
-      };
-      Frag af[2][4], bf[2];
+    for (int t = 0; t < 4; ++t) fa[t] = frag(As[pa0][0] + (wm + t * 16 + r16) * LDE);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int ro = (wm + t * 16 + r16) * LDE;
-        af[0][t] = frag(As[pa0][0] + ro);
-        af[1][t] = pa1 != pa0 ? frag(As[pa1][0] + ro) : af[0][t];
-      }
-#pragma unroll
-      for (int t = 0; t < 2; ++t) bf[t] = frag(Bs[0] + (wn + t * 16 + r16) * LDE);
+    for (int t = 0; t < NB; ++t) fb[t] = frag(Bs[0] + (wn + t * 16 + r16) * LDE);
+  };
+  auto mfma_frags = [&](const Frag (&fa)[4], const Frag (&fb)[NB]) {
+    if constexpr (PREC != PREC_BF16) {
 #pragma unroll
       for (int i = 0; i < KQ; ++i)
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
+          for (int b = 0; b < NB; ++b) {
             if constexpr (PREC == PREC_F64)
-              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[b][a].x[i], bf[b].x[i],
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].x[i], fb[b].x[i],
                                                                acc[a][b], 0, 0, 0);
             else
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[b][a].x[i], bf[b].x[i],
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a].x[i], fb[b].x[i],
                                                                acc[a][b], 0, 0, 0);
           }
     }
   };
-  if constexpr (lds_stages<PREC, KX>() == 2) {
+  if constexpr (PREC != PREC_BF16) {
+    // Two LDS stages and two register sets of fragments.  Step kt issues the MFMAs of slice kt
+    // from registers while the fragments of slice kt+1 are read from LDS, slice kt+2 is stored
+    // into the stage slice kt came from (read into registers before the previous barrier) and
+    // slice kt+3 is loading from global memory: one barrier per slice, and the matrix cores
+    // never wait for an LDS read.
+    Frag fa0[4], fb0[NB], fa1[4], fb1[NB];
+    gload(sl0, 0);
+    sstore(sl0, 0);
+    if (KT > 1) gload(sl0, BK);
+    __syncthreads();
+    read_frags(0, fa0, fb0);
+    if (KT > 1) {
+      sstore(sl0, 1);
+      if (KT > 2) gload(sl0, 2 * BK);
+    }
+    __syncthreads();
+    auto step = [&](int kt, const Frag (&ca)[4], const Frag (&cb)[NB], Frag (&na)[4],
+                    Frag (&nb)[NB]) {
+      if (kt + 1 < KT) read_frags((kt + 1) & 1, na, nb);
+      if (kt + 2 < KT) {
+        sstore(sl0, kt & 1);
+        if (kt + 3 < KT) gload(sl0, (kt + 3) * BK);
+      }
+      mfma_frags(ca, cb);
+      __syncthreads();
+    };
+    for (int kt = 0; kt < KT; kt += 2) {
+      step(kt, fa0, fb0, fa1, fb1);
+      if (kt + 1 < KT) step(kt + 1, fa1, fb1, fa0, fb0);
+    }
+  } else if constexpr (lds_stages<PREC, KX>() == 2) {
     // two LDS stages: slice kt + 1 is stored into the other stage (last read before the
     // previous barrier) while slice kt feeds the matrix cores; slice kt + 2 is loading meanwhile
     gload(sl0, 0);
@@ -737,7 +776,7 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   typedef typename std::conditional<PREC == PREC_F64, double, float>::type ST;
   constexpr int RJ = PREC == PREC_F64 ? 16 : 32;              // output rows per round
   constexpr int SS = BT + 16 / (int)sizeof(ST);               // LDS row stride, 16-byte rows
-  constexpr int ET = RJ * BT / NTHR;                          // elements per thread: 4 or 8
+  constexpr int ET = RJ * BT / NTHR;                          // elements per thread: 4 to 16
   static_assert(RJ * SS * sizeof(ST) <= sizeof(As[0]), "staging fits the A buffer");
   ST* stg = reinterpret_cast<ST*>(&As[0][0][0]);
   double* out64 = nullptr;
@@ -775,9 +814,9 @@ __global__ __launch_bounds__(NTHR) void k_pass2d(const Pass2D* __restrict__ pass
   for (int jr = 0; jr < BT; jr += RJ) {
     const int cur = (jr / RJ) & 1;
     __syncthreads();                                  // the buffer is free
-    if (wn <= jr && jr < wn + 32) {                   // this wave holds rows jr .. jr + RJ
+    if (wn <= jr && jr < wn + WC) {                   // this wave holds rows jr .. jr + RJ
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < NB; ++b) {
         const int jl0 = wn + 16 * b;
         if (jl0 < jr || jl0 >= jr + RJ) continue;
 #pragma unroll
@@ -938,29 +977,58 @@ bool wide_slices(int64_t n) {
   return PREC == PREC_BF16 && folded(n) && (n / 2) % (2 * Tr<PREC>::BK) == 0;
 }
 
+// 64-column waves (tile bit kPassWide64) are possible when the fold cannot split a wave's
+// columns between sums and differences (n/2 a multiple of 64, or no fold), for the FP32 and
+// FP64 passes; the split-BF16 pass takes 64-wide k-slices unless tile bit kPassNarrowK asks for
+// 32-wide ones.  Every shape issues the same MFMA sequence for every output element.
+template <int PREC>
+bool wide_waves(int64_t n, int tile) {
+  return PREC != PREC_BF16 && (tile & kPassWide64) && (!folded(n) || n % 128 == 0);
+}
+
 template <int PREC, int OUT>
 void launch_pass(const Pass2D* d, const Lvl2D* lv, int count, int64_t nmax, int64_t sigma,
-                 hipStream_t st) {
+                 int tile, hipStream_t st) {
   const unsigned t = (unsigned)((nmax + BT - 1) / BT);
   const dim3 grid(t, t, count);
   const size_t full = pass_lds_bytes<PREC, 1>(0), fold = pass_lds_bytes<PREC, 1>(1);
   const size_t wide = pass_lds_bytes<PREC, 2>(1);
+  if constexpr (PREC != PREC_BF16) {
+    if (wide_waves<PREC>(nmax, tile)) {
+      if (!folded(nmax))
+        hipLaunchKernelGGL((k_pass2d<PREC, OUT, 0, 1, 64>), grid, dim3(pass_threads<64>()), full,
+                           st, d, lv, sigma);
+      else
+        hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 1, 64>), grid, dim3(pass_threads<64>()), fold,
+                           st, d, lv, sigma);
+      return;
+    }
+  }
   if (!folded(nmax)) {
-    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 0, 1>), grid, dim3(NTHR), full, st, d, lv, sigma);
-  } else if (!wide_slices<PREC>(nmax)) {
-    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 1>), grid, dim3(NTHR), fold, st, d, lv, sigma);
+    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 0, 1, 32>), grid, dim3(pass_threads<32>()), full, st,
+                       d, lv, sigma);
+  } else if (!wide_slices<PREC>(nmax) || (tile & kPassNarrowK)) {
+    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 1, 32>), grid, dim3(pass_threads<32>()), fold, st,
+                       d, lv, sigma);
   } else {
     if constexpr (PREC == PREC_BF16)
-      hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 2>), grid, dim3(NTHR), wide, st, d, lv, sigma);
+      hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 2, 32>), grid, dim3(pass_threads<32>()), wide,
+                         st, d, lv, sigma);
   }
 }
 
 // Allow the pass variants their LDS (host call, outside any stream capture).
 template <int PREC, int OUT, int FOLD, int KX>
 hipError_t allow_lds() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass2d<PREC, OUT, FOLD, KX>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)pass_lds_bytes<PREC, KX>(FOLD));
+  hipError_t e = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&k_pass2d<PREC, OUT, FOLD, KX, 32>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)pass_lds_bytes<PREC, KX>(FOLD));
+  if constexpr (PREC != PREC_BF16 && KX == 1)
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass2d<PREC, OUT, FOLD, KX, 64>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)pass_lds_bytes<PREC, KX>(FOLD));
+  return e;
 }
 
 // every variant a precision launches: its own output type and the final update, folded or not
@@ -1107,11 +1175,35 @@ int plan2d_create(const ridc_problem* p, double h, double* const* ring, const in
   }
   RIDC_HIP_TRY(hipMemcpy(pl->d_passes, pl->passes.data(), sizeof(Pass2D) * pl->passes.size(),
                          hipMemcpyHostToDevice));
+  {
+    // the measured pass shape of this (n, precision), if the tuning table has one
+    int tile = 0;
+    if (tune_get_2d(p->n, p->prec, &tile)) (void)plan2d_set_tile(pl, tile);
+    set_error("");
+  }
   *out = pl;
   return RIDC_OK;
 }
 
 void plan2d_destroy(Plan2D* pl) { delete pl; }
+
+int plan2d_tile(const Plan2D* pl) { return pl->tile; }
+
+void plan2d_tile_candidates(const Plan2D* pl, std::vector<int>* out) {
+  out->clear();
+  out->push_back(0);
+  if (pl->prec != PREC_BF16 && (!folded(pl->n) || pl->n % 128 == 0)) out->push_back(kPassWide64);
+  if (pl->prec == PREC_BF16 && wide_slices<PREC_BF16>(pl->n)) out->push_back(kPassNarrowK);
+}
+
+int plan2d_set_tile(Plan2D* pl, int tile) {
+  std::vector<int> c;
+  plan2d_tile_candidates(pl, &c);
+  if (std::find(c.begin(), c.end(), tile) == c.end())
+    return fail(RIDC_E_INVAL, "launch shape not available for this side and precision");
+  pl->tile = tile;
+  return RIDC_OK;
+}
 
 int plan2d_arm(Plan2D* pl, int64_t nt, hipStream_t stream) {
   for (auto& L : pl->levels) {
@@ -1129,33 +1221,33 @@ namespace {
 // right-hand side, the transform passes and (reduced precision) the residual, one launch each.
 // passes is pass-major: passes[k * cnt + e].
 void run_stages(int prec, const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nmax, int64_t s,
-                hipStream_t st) {
+                int tile, hipStream_t st) {
   launch_stencil(k_rhs2d, lv, cnt, nmax, s, st);
   if (prec == PREC_F64) {
-    launch_pass<PREC_F64, OUT_F64>(d + 0 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F64, OUT_F64>(d + 1 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F64, OUT_F64>(d + 2 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F64, OUT_FINAL>(d + 3 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F64, OUT_F64>(d + 0 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_F64, OUT_F64>(d + 1 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_F64, OUT_F64>(d + 2 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_F64, OUT_FINAL>(d + 3 * cnt, lv, cnt, nmax, s, tile, st);
   } else if (prec == PREC_F32) {
-    launch_pass<PREC_F32, OUT_F32>(d + 0 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 3 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 0 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 3 * cnt, lv, cnt, nmax, s, tile, st);
     launch_stencil(k_resid2d, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F32, OUT_FINAL>(d + 7 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_F32, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_F32, OUT_FINAL>(d + 7 * cnt, lv, cnt, nmax, s, tile, st);
   } else {
-    launch_pass<PREC_BF16, OUT_F32>(d + 0 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 3 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 0 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 3 * cnt, lv, cnt, nmax, s, tile, st);
     launch_stencil(k_resid2d, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_FINAL>(d + 7 * cnt, lv, cnt, nmax, s, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_BF16, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC_BF16, OUT_FINAL>(d + 7 * cnt, lv, cnt, nmax, s, tile, st);
   }
 }
 
@@ -1234,15 +1326,16 @@ int plan2d_advance(Plan2D* const* pls, int count, const int64_t* sigma_before, i
   if (count == 1) {
     Plan2D* pl = pls[0];
     for (int64_t s = 1; s <= steps; ++s)
-      run_stages(pl->prec, pl->d_levels, pl->d_passes, pl->P, pl->n, sigma_before[0] + s, stream);
+      run_stages(pl->prec, pl->d_levels, pl->d_passes, pl->P, pl->n, sigma_before[0] + s, pl->tile,
+                 stream);
     RIDC_HIP_TRY(hipGetLastError());
     return RIDC_OK;
   }
-  // groups keyed by (prec, n), in first-seen order
+  // groups keyed by (prec, n, launch shape), in first-seen order
   std::vector<std::pair<std::pair<int, int64_t>, std::vector<int>>> groups;
   size_t nlv = 0, nps = 0;
   for (int i = 0; i < count; ++i) {
-    const auto key = std::make_pair(pls[i]->prec, pls[i]->n);
+    const auto key = std::make_pair(pls[i]->prec | (pls[i]->tile << 8), pls[i]->n);
     auto it = std::find_if(groups.begin(), groups.end(), [&](auto& g) { return g.first == key; });
     if (it == groups.end()) {
       groups.push_back({key, {}});
@@ -1258,15 +1351,16 @@ int plan2d_advance(Plan2D* const* pls, int count, const int64_t* sigma_before, i
     int prec, cnt;
     int64_t n;
     size_t lv_off, ps_off;
+    int tile;
   };
   std::vector<G> gs;
   size_t lo = 0, po = 0;
   for (auto& g : groups) {
-    const int prec = g.first.first;
+    const int prec = g.first.first & 0xff;
     const int npass = prec == PREC_F64 ? 4 : 8;
     int cnt = 0;
     for (int i : g.second) cnt += pls[i]->P;
-    G gg{prec, cnt, g.first.second, lo, po};
+    G gg{prec, cnt, g.first.second, lo, po, g.first.first >> 8};
     int e = 0;
     for (int i : g.second) {
       Plan2D* pl = pls[i];
@@ -1292,7 +1386,8 @@ int plan2d_advance(Plan2D* const* pls, int count, const int64_t* sigma_before, i
   g_a2.pending = true;
   for (int64_t s = 1; s <= steps; ++s)
     for (auto& g : gs)
-      run_stages(g.prec, g_a2.d_lv + g.lv_off, g_a2.d_ps + g.ps_off, g.cnt, g.n, s, stream);
+      run_stages(g.prec, g_a2.d_lv + g.lv_off, g_a2.d_ps + g.ps_off, g.cnt, g.n, s, g.tile,
+                 stream);
   RIDC_HIP_TRY(hipGetLastError());
   RIDC_HIP_TRY(hipEventRecord(g_a2.used, stream));
   g_a2.used_stream = stream;
@@ -1310,11 +1405,12 @@ int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, do
   RIDC_HIP_TRY(hipEventCreate(&b));
   auto one = [&]() {
     if (pl->prec == PREC_F64)
-      launch_pass<PREC_F64, OUT_F64>(pl->d_passes, pl->d_levels, P, n, sigma, stream);
+      launch_pass<PREC_F64, OUT_F64>(pl->d_passes, pl->d_levels, P, n, sigma, pl->tile, stream);
     else if (pl->prec == PREC_F32)
-      launch_pass<PREC_F32, OUT_F32>(pl->d_passes, pl->d_levels, P, n, sigma, stream);
+      launch_pass<PREC_F32, OUT_F32>(pl->d_passes, pl->d_levels, P, n, sigma, pl->tile, stream);
     else
-      launch_pass<PREC_BF16, OUT_F32>(pl->d_passes, pl->d_levels, P, n, sigma, stream);
+      launch_pass<PREC_BF16, OUT_F32>(pl->d_passes, pl->d_levels, P, n, sigma, pl->tile,
+                                      stream);
   };
   one();
   (void)hipEventRecord(a, stream);

@@ -206,6 +206,22 @@ hipError_t launch_imex1d(const ImexLvl* d_items, int count, int M, int threads, 
                          int64_t sigma, bool init, hipStream_t stream);
 
 // ---------------------------------------------------------------------------------------------
+// persistent table of measured launch shapes (tune.cpp)
+// ---------------------------------------------------------------------------------------------
+// 1D level-step tiling per (n, boundary, PCR stages), as ridc_set_tile's (threads, rows, flags)
+bool tune_get_1d(int64_t n, int bc, int stages, int* threads, int* rows, int* flags);
+void tune_put_1d(int64_t n, int bc, int stages, int threads, int rows, int flags);
+// grouped 1D tiling, as ridc_set_batch_tile's (threads, rows)
+bool tune_get_batch(int* threads, int* rows);
+void tune_put_batch(int threads, int rows);
+// 2D transform-pass shape per (n, precision)
+bool tune_get_2d(int64_t n, int prec, int* tile);
+void tune_put_2d(int64_t n, int prec, int tile);
+int tune_save(const char* path);   // nullptr: the default file
+int tune_load(const char* path);
+void tune_clear();
+
+// ---------------------------------------------------------------------------------------------
 // allocation-free 1D integration (noalloc.hip): a fixed scratch array per GPU
 // ---------------------------------------------------------------------------------------------
 constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;   // 32 MiB per GPU

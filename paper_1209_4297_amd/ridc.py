@@ -103,6 +103,9 @@ def _load():
         "ridc_stage_weights": (ctypes.c_int, [i32, i32, i32, i32,
                                               ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_double)]),
+        "ridc_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+        "ridc_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+        "ridc_tune_clear": (ctypes.c_int, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -119,7 +122,7 @@ EXPORTED = ("ridc_create", "ridc_destroy", "ridc_footprint_bytes", "ridc_integra
             "ridc_kernel_time", "ridc_integrate_restarts", "ridc_set_batch_tile",
             "ridc_autotune_batch", "ridc_batch_kernel_time", "ridc_stencil_time",
             "ridc_integrate_noalloc", "ridc_create_ext", "ridc_footprint_bytes_ext",
-            "ridc_stage_weights")
+            "ridc_stage_weights", "ridc_tune_save", "ridc_tune_load", "ridc_tune_clear")
 
 
 def lib():
@@ -373,6 +376,21 @@ def integrate_noalloc(prob: dict, u0, nsteps: int, uT=None, nonfinite=None, dt=N
     return uT
 
 
+def tune_save(path: str | None = None):
+    """Write the tuning table (measured launch shapes) to ``path`` (None: the default cache)."""
+    _check(_lib.ridc_tune_save(path.encode() if path else None))
+
+
+def tune_load(path: str | None = None):
+    """Merge the launch shapes recorded in ``path`` (None: the default cache) into the table."""
+    _check(_lib.ridc_tune_load(path.encode() if path else None))
+
+
+def tune_clear():
+    """Forget every recorded launch shape (the autotuners measure again)."""
+    _check(_lib.ridc_tune_clear())
+
+
 def pipeline_steps(nt: int, order: int) -> int:
     return nt + order * (order - 1) // 2 if nt > 0 else 0
 
@@ -384,6 +402,7 @@ def grid_h(prob: dict) -> float:
 
 __all__ = ["Ridc", "RidcError", "advance", "integrate_batch", "set_batch_tile", "autotune_batch",
            "batch_kernel_time", "integrate_noalloc", "make_ext", "uses_ext", "stage_weights",
+           "tune_save", "tune_load", "tune_clear",
            "make_problem", "footprint_bytes",
            "quadrature_weights", "pcr_plan", "pipeline_steps", "library_path", "lib", "EXPORTED",
            "math"]

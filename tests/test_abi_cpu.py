@@ -195,3 +195,31 @@ def test_ext_validation_and_footprint(ridc):
     e.reserved = 1
     assert lib.ridc_create_ext(ctypes.byref(p), ctypes.byref(e), None, ctypes.byref(out)) == \
         ridc.RIDC_E_INVAL
+
+
+def test_tune_cache_round_trip(ridc, tmp_path):
+    """The tuning table's file format: entries loaded from a file are written back unchanged
+    (1D tilings, the grouped tiling, 2D pass shapes); unreadable files are errors."""
+    import json
+    doc = {"format": "ridc-tune-1", "device": "",
+           "tile1d": [{"n": 8192, "bc": 1, "stages": 13, "threads": 1024, "rows": 128,
+                       "flags": 1},
+                      {"n": 128, "bc": 0, "stages": 7, "threads": 512, "rows": 0, "flags": 2}],
+           "batch1d": {"threads": 512, "rows": 1536},
+           "pass2d": [{"n": 1024, "prec": 2, "tile": 2}, {"n": 512, "prec": 0, "tile": 1}]}
+    src = tmp_path / "in.json"
+    src.write_text(json.dumps(doc))
+    ridc.tune_clear()
+    ridc.tune_load(str(src))
+    out = tmp_path / "sub" / "out.json"
+    ridc.tune_save(str(out))
+    got = json.loads(out.read_text())
+    assert got["format"] == "ridc-tune-1"
+    for key in ("tile1d", "pass2d"):
+        assert sorted(got[key], key=json.dumps) == sorted(doc[key], key=json.dumps)
+    assert got["batch1d"] == doc["batch1d"]
+    ridc.tune_clear()
+    ridc.tune_save(str(out))
+    assert json.loads(out.read_text())["tile1d"] == []
+    with pytest.raises(ridc.RidcError):
+        ridc.tune_load(str(tmp_path / "missing.json"))
