@@ -743,19 +743,61 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
       if (kt + 1 < KT) step(kt + 1, fa1, fb1, fa0, fb0);
     }
   } else if constexpr (lds_stages<PREC, KX>() == 2) {
-    // two LDS stages: slice kt + 1 is stored into the other stage (last read before the
-    // previous barrier) while slice kt feeds the matrix cores; slice kt + 2 is loading meanwhile
+    // split BF16, 32-wide slices in two LDS stages: the schedule of the FP32/FP64 passes, with
+    // the hi/lo fragments of a slice (one 32-wide k-step) double-buffered in registers
+    struct FragB {
+      bf16x8 ahi[4], alo[4], bhi[2], blo[2];
+    };
+    auto read_frags_bf = [&](int stage, FragB& f) {
+      T (*As)[NSPLIT][BT * LDE] = stage_a(stage);
+      T (*Bs)[BT * LDE] = stage_b(stage);
+      const int kb = (lane >> 4) * 16;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int ro = (wm + t * 16 + r16) * ROWB + kb;
+        f.ahi[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa0][0] + ro));
+        f.alo[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)As[pa0][1] + ro));
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int ro = (wn + t * 16 + r16) * ROWB + kb;
+        f.bhi[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)Bs[0] + ro));
+        f.blo[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)Bs[1] + ro));
+      }
+    };
+    auto mfma_bf = [&](const FragB& f) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.alo[a], f.bhi[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ahi[a], f.blo[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ahi[a], f.bhi[b], acc[a][b], 0, 0, 0);
+        }
+    };
+    FragB f0, f1;
     gload(sl0, 0);
     sstore(sl0, 0);
     if (KT > 1) gload(sl0, BK);
     __syncthreads();
-    for (int kt = 0; kt < KT; ++kt) {
-      if (kt + 1 < KT) {
-        sstore(sl0, (kt + 1) & 1);
-        if (kt + 2 < KT) gload(sl0, (kt + 2) * BK);
+    read_frags_bf(0, f0);
+    if (KT > 1) {
+      sstore(sl0, 1);
+      if (KT > 2) gload(sl0, 2 * BK);
+    }
+    __syncthreads();
+    auto step_bf = [&](int kt, const FragB& cur, FragB& next) {
+      if (kt + 1 < KT) read_frags_bf((kt + 1) & 1, next);
+      if (kt + 2 < KT) {
+        sstore(sl0, kt & 1);
+        if (kt + 3 < KT) gload(sl0, (kt + 3) * BK);
       }
-      mfma_slice(kt & 1);
+      mfma_bf(cur);
       __syncthreads();
+    };
+    for (int kt = 0; kt < KT; kt += 2) {
+      step_bf(kt, f0, f1);
+      if (kt + 1 < KT) step_bf(kt + 1, f1, f0);
     }
   } else {
     // wide slices: one in flight, its loads cover a whole MFMA phase of twice the length
