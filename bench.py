@@ -48,12 +48,12 @@ MEASURED_TRAFFIC = {
     ("reacdiff1d", (1024, 128, 0)): ("1d", "564458ee427cc4d1", 4530176),
     ("batched1d", (256, 1536)): ("1d", "564458ee427cc4d1", 72678016),
     ("batched1d", (512, 1536)): ("1d", "564458ee427cc4d1", 72604672),
-    ("reacdiff2d_rhs", "fp64"): ("2d", "68f9a3aadc30cd63", 185682816),
-    ("reacdiff2d", "fp64"): ("2d", "68f9a3aadc30cd63", 100888576),
-    ("reacdiff2d_rhs", "fp32"): ("2d", "68f9a3aadc30cd63", 202901888),
-    ("reacdiff2d", "fp32"): ("2d", "68f9a3aadc30cd63", 50556672),
-    ("reacdiff2d_rhs", "bf16x3"): ("2d", "68f9a3aadc30cd63", 202799360),
-    ("reacdiff2d", "bf16x3"): ("2d", "68f9a3aadc30cd63", 50584320),
+    ("reacdiff2d_rhs", "fp64"): ("2d", "f665aa3c456117d7", 185794055),
+    ("reacdiff2d", "fp64"): ("2d", "f665aa3c456117d7", 100917722),
+    ("reacdiff2d_rhs", "fp32"): ("2d", "f665aa3c456117d7", 202970027),
+    ("reacdiff2d", "fp32"): ("2d", "f665aa3c456117d7", 50584031),
+    ("reacdiff2d_rhs", "bf16x3"): ("2d", "f665aa3c456117d7", 202870307),
+    ("reacdiff2d", "bf16x3"): ("2d", "f665aa3c456117d7", 50570802),
 }
 
 
