@@ -2,8 +2,15 @@
 the matrix cores) against the FP64 oracle.
 
 FP64: relative L2 <= 1e-12 per level.  Reduced precision (FP32 or split-BF16 transforms with
-one FP64 residual refinement) has the stated tolerances below; both are far below the RIDC4
-discretisation error of these cases.
+one FP64 residual refinement): a bound per level index (TOL), about 100 x the largest error
+measured for that level over these cases, the full-size case and the served requests (FP32:
+4.2e-15, 7.4e-16, 7.0e-16, 5.1e-16 for levels 0-3; split BF16: 1.5e-11, 2.7e-12, 3.2e-14,
+3.1e-15), with the RIDC4 top level capped at 1.5e-13 = 0.1 x the discretisation error of the
+1024^2 workload (1.5e-12, Richardson), the bar at which a reduced-precision result counts as
+matched.  The lower levels of the split-BF16 path sit far above the top level: each level's
+increment is solved to about 1e-11 of itself, and a level's error against the oracle is small
+next to its own discretisation error (level 0 is first order).  Every bound holds for the
+relative L2 error and for the largest pointwise error relative to the largest value.
 """
 import math
 import os
@@ -17,8 +24,7 @@ from oracle import Problem, rel_l2, ridc_pipelined
 
 pytestmark = pytest.mark.gpu
 
-TOL64 = 1e-12
-TOL = {"fp32": 1e-11, "bf16x3": 1e-8}
+from tolerances import TOL64, tol_of  # noqa: E402  (per-level bounds, derivation above)
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "reacdiff2d_n1024_nt500.npz")
 
 
@@ -86,7 +92,7 @@ def test_mixed_precision_parity(env, prec, n, nt):
     for j in range(4):
         err, emax = errs(lvs[j], ref[j])
         _say(f"  level {j}: rel L2 {err:.3e}, max {emax:.3e}")
-        assert err <= TOL[prec] and emax <= TOL[prec], (j, err, emax)
+        assert err <= tol_of(prec, j) and emax <= tol_of(prec, j), (j, err, emax)
 
 
 def test_largest_side_sine_mode_closed_form(env):
@@ -165,13 +171,15 @@ def test_full_size_against_reference_samples(env, prec):
     _say(f"case: 2D {prec} full n=1024 nt=500")
     top, lvs = run2d(env, prob, u0, prec=prec)
     idx = ref["idx"]
-    tol = TOL64 if prec == "fp64" else TOL[prec]
     for j in range(4):
+        tol = tol_of(prec, j)
         flat = lvs[j].reshape(-1)
         err, emax = errs(flat[idx], ref["samples"][j])
         nerr = abs(np.linalg.norm(flat) - ref["norms"][j]) / ref["norms"][j]
         _say(f"  level {j}: sampled rel L2 {err:.3e}, max {emax:.3e}, norm rel diff {nerr:.3e}")
         assert err <= tol and emax <= tol and nerr <= tol, (j, err, emax, nerr)
+    # the result (top level): matched when within 0.1 x the RIDC4 discretisation error
+    tol = tol_of(prec, 3)
     err, emax = errs(top[::8, ::8], ref["top_sub8"])
     _say(f"  top level on the 128^2 sub-grid: rel L2 {err:.3e}, max {emax:.3e}")
     assert err <= tol and emax <= tol
