@@ -243,9 +243,9 @@ int ridc_step_cost(const ridc_handle* h, double* hbm_bytes, double* flops);
  *    cycle; flags as in ridc_set_tile).
  *  - 2D: the transform-pass shapes the handle's side and precision allow, keyed by (n,
  *    precision): 32- or 64-column waves (FP32/FP64 passes), 64- or 32-wide k-slices
- *    (split-BF16 pass), each timed over 20 launches of a pass.  threads_out receives the
- *    threads per block, rows_out 0, flags_out the shape bits (1: 64-column waves, 2: 32-wide
- *    slices).
+ *    (split-BF16 pass), prefolded or row-major intermediates (n a multiple of 256), each
+ *    timed over 20 launches of a pass.  threads_out receives the threads per block, rows_out
+ *    0, flags_out the shape bits as in ridc_set_tile.
  * A shape already recorded for the key (this process, or the tuning cache file) is applied
  * without measuring; ridc_tune_clear forgets the table.  Every shape performs the same
  * operations for every output value, so results are bitwise independent of the choice.  The
@@ -254,8 +254,10 @@ int ridc_step_cost(const ridc_handle* h, double* hbm_bytes, double* flops);
 int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out);
 
 /* 2D handles: set the transform-pass shape bits `flags` (1: 64-column waves, FP32/FP64 passes
- * with n/2 a multiple of 64 or no fold; 2: 32-wide k-slices, split-BF16 pass; 0: the default);
- * rows must be 0 and threads is ignored; results do not depend on the shape.
+ * with n/2 a multiple of 64 or no fold; 2: 32-wide k-slices, split-BF16 pass; 4: row-major
+ * intermediates folded while staging, instead of the folded planes (sums and differences of
+ * mirrored columns) that the passes exchange by default when n is a multiple of 256; 0: the
+ * default); rows must be 0 and threads is ignored; results do not depend on the shape.
  * 1D: force a tiling: threads in {64,128,256,512,1024}; rows = 0 for the whole cycle in one
  * workgroup, else chunks of `rows` rows (allowed when the PCR coupling vanishes within a halo
  * shorter than the system); flags bit 0 = write level values with nontemporal stores; flags

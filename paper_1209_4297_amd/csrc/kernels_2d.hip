@@ -45,7 +45,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
-enum { OUT_F64 = 0, OUT_F32 = 1, OUT_FINAL = 3 };
+enum { OUT_F64 = 0, OUT_F32 = 1, OUT_FINAL = 3, OUT_FOLD = 4 };
 
 // One (instance, level) of the 2D pipeline: static for a handle.
 struct Lvl2D {
@@ -421,6 +421,25 @@ __device__ __forceinline__ u32x4 fold1_f32(u32x4 a, u32x4 m, float sg) {
 }
 
 
+// Instruction order of one pipelined k-slice step (a single basic block): NR LDS reads, then
+// NW LDS writes and global loads, each placed after one of the step's NM MFMAs, and the rest of
+// the MFMAs after them.  Groups with no instruction left to take stay empty.
+template <int NM, int NR, int NW>
+__device__ __forceinline__ void interleave_step() {
+  static_assert(NR + NW <= NM, "one MFMA per memory instruction");
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+  }
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x210, 1, 0);   // LDS write or global load
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, NM - NR - NW, 0);
+}
+
 // FOLD (n a multiple of 64): the contraction runs over k < n/2 with the folded A operands and
 // E.Q the folded transform: row j' (n rows) holds Q_{k, perm(j')} for k < n/2, perm(j') = 2j'
 // for j' < n/2 and 2(j' - n/2) + 1 above; output column j' of the block grid is column perm(j').
@@ -433,16 +452,23 @@ template <int PREC, int KX>
 constexpr int lds_stages() {
   return PREC == PREC_BF16 && KX == 2 ? 1 : 2;
 }
-template <int PREC, int KX>
+// A operand tiles per LDS stage: the folded sums and differences when the pass folds while
+// staging (a block with output columns on both sides of n/2 needs both), else one
+template <int FOLD, int AIN>
+constexpr int a_tiles() {
+  return FOLD && !AIN ? 2 : 1;
+}
+template <int PREC, int KX, int AIN>
 constexpr size_t pass_lds_bytes(int fold) {
   typedef typename Tr<PREC>::T T;
   constexpr int BK = Tr<PREC>::BK * KX;
   constexpr int LDE = (BK * (int)sizeof(T) + 16) / (int)sizeof(T);
   constexpr int NSPLIT = PREC == PREC_BF16 ? 2 : 1;
-  return (size_t)lds_stages<PREC, KX>() * ((fold ? 2 : 1) * NSPLIT + NSPLIT) * BT * LDE * sizeof(T);
+  const int na = fold && !AIN ? 2 : 1;
+  return (size_t)lds_stages<PREC, KX>() * (na * NSPLIT + NSPLIT) * BT * LDE * sizeof(T);
 }
 
-template <int PREC, int OUT, int FOLD, int KX, int WC>
+template <int PREC, int OUT, int FOLD, int KX, int WC, int AIN>
 __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __restrict__ passes,
                                                                const Lvl2D* __restrict__ levels,
                                                                int64_t sigma) {
@@ -457,7 +483,9 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
   constexpr int CH = BK * (int)sizeof(T) / 16;        // 16-byte chunks per row
   constexpr int NSPLIT = PREC == PREC_BF16 ? 2 : 1;
   constexpr int CPT = BT * CH / NTHR;                 // chunks per thread per operand and split
-  constexpr int NA = FOLD ? 2 : 1;                    // A operands: (folded sums, differences)
+  constexpr int NA = a_tiles<FOLD, AIN>();           // A operands in LDS (folded sums, diffs)
+  static_assert(!AIN || FOLD, "prefolded operands exist for folded transforms only");
+  static_assert(OUT != OUT_FOLD || FOLD, "a folded output needs the folded transform");
   extern __shared__ __attribute__((aligned(16))) unsigned char pass_smem[];
   // LDS stage b of a k-slice: the A operands, then Q
   constexpr size_t A_BYTES = (size_t)NA * NSPLIT * BT * LDE * sizeof(T);
@@ -490,9 +518,15 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
   int64_t m;
   if (!level_active(L, sigma, &m)) return;
   const int n = L.n;
-  const int row0 = by * BT;                  // rows of A (i)
+  // Rows of A (i) of the block: BT consecutive rows from row0, or, when the epilogue folds its
+  // output for the next pass, the mirrored pairs row0 + t and n-1-row0-t (t < BT/2) at local
+  // rows t and BT/2 + t, so that the block holds both columns of every folded pair of C^T.
+  constexpr bool MIRROR = OUT == OUT_FOLD;
+  constexpr int HB = BT / 2;
+  const int row0 = MIRROR ? by * HB : by * BT;
   const int col0 = bx * BT;                  // columns of Q (j)
-  if (row0 >= n || col0 >= n) return;
+  if ((MIRROR ? 2 * row0 : row0) >= n || col0 >= n) return;
+  auto a_row = [&](int r) { return MIRROR ? (r < HB ? row0 + r : n - 1 - row0 - (r - HB)) : row0 + r; };
   const int64_t nn = (int64_t)n * n;
   // A arrives in FP64 or FP32 (the split-BF16 pass splits it while staging); Q in T
   typedef typename std::conditional<PREC == PREC_BF16, float, T>::type TA;
@@ -504,6 +538,10 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
   const int K = FOLD ? n / 2 : n;                   // contraction length
   const int64_t qsplit = (int64_t)n * K;            // BF16: lo part of the transform
   constexpr int E16 = 16 / (int)sizeof(T);          // elements per 16-byte chunk
+  // prefolded operands: planes (side, split) of n rows x n/2 elements of T, side 0 the sums
+  // A_{i,k} + A_{i,n-1-k} and side 1 the differences (BF16: split into hi, lo), each n x n/2
+  const T* Ap = (const T*)E.A;
+  const int64_t plane = (int64_t)n * K;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -518,22 +556,36 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
     for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
   // global -> register staging of one k-slice (A, its mirrored columns when folding, Q); a
-  // slice's loads are issued one MFMA phase before they are stored into LDS
+  // slice's loads are issued one MFMA phase before they are stored into LDS.  Rows past n (a
+  // partial block tile) read row n-1 instead: they only reach output rows or columns past n,
+  // which the epilogue never stores, and no select on the loaded values makes a step wait for
+  // its loads.
   struct Slice {
-    u32x4 ra[NAC], rm[NAC], rb[NSPLIT][CPT];
+    u32x4 ra[NAC], rm[NAC], rp[NSPLIT][CPT], rb[NSPLIT][CPT];
   };
   Slice sl0;
+  const int side = FOLD && col0 >= (n >> 1) ? 1 : 0;
   auto gload = [&](Slice& S, int k0) {
+    if constexpr (AIN) {
 #pragma unroll
-    for (int c = 0; c < NAC; ++c) {
+      for (int s = 0; s < NSPLIT; ++s)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          const int id = tid + c * NTHR;
+          const int r = id / CH, q = id % CH;
+          S.rp[s][c] = gld<u32x4>(Ap + (side * NSPLIT + s) * plane + (int64_t)a_row(r) * K + k0 +
+                                  q * E16);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < (AIN ? 0 : NAC); ++c) {
       const int id = tid + c * NTHR;
       const int r = id / CHA, q = id % CHA;
-      const int ga = row0 + r;
+      const int ga = a_row(r);
       const int64_t ko = k0 + q * EA;
-      const TA* arow = A + (int64_t)ga * n;
-      S.ra[c] = ga < n ? gld<u32x4>(arow + ko) : u32x4{0, 0, 0, 0};
-      if constexpr (FOLD)
-        S.rm[c] = ga < n ? gld<u32x4>(arow + (n - ko - EA)) : u32x4{0, 0, 0, 0};
+      const TA* arow = A + (int64_t)(ga < n ? ga : n - 1) * n;
+      S.ra[c] = gld<u32x4>(arow + ko);
+      if constexpr (FOLD) S.rm[c] = gld<u32x4>(arow + (n - ko - EA));
     }
 #pragma unroll
     for (int s = 0; s < NSPLIT; ++s)
@@ -543,14 +595,22 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
         const int r = id / CH, q = id % CH;
         const int gb = col0 + r;                        // Q symmetric: row j of Q = column j
         const int64_t ko = k0 + q * E16;
-        S.rb[s][c] = gb < n ? gld<u32x4>(Q + s * qsplit + (int64_t)gb * K + ko)
-                            : u32x4{0, 0, 0, 0};
+        S.rb[s][c] = gld<u32x4>(Q + s * qsplit + (int64_t)(gb < n ? gb : n - 1) * K + ko);
       }
   };
   // a block whose output columns all lie on one side of n/2 needs only the sums (side 0) or
   // only the differences (side 1)
   const bool one_side = FOLD && (col0 + BT <= (n >> 1) || col0 >= (n >> 1));
-  const int side = FOLD && col0 >= (n >> 1) ? 1 : 0;
+  // The main loops take one_side at compile time (os: std::true_type when the block needs one
+  // side of the fold), so that a pipelined step holds no branch.
+  auto with_side = [&](auto&& loop) {
+    if constexpr (FOLD && !AIN) {
+      if (one_side) loop(std::true_type{});
+      else loop(std::false_type{});
+    } else {
+      loop(std::false_type{});
+    }
+  };
   // FP32/FP64 operand rows keep a k-slice permuted, k at (k % 4) * KQ + k / 4, so that the KQ
   // values one lane consumes over the slice (k = 4i + lane/16) are contiguous; BF16 rows keep
   // k in order (its instruction takes 8 consecutive k per lane).
@@ -571,11 +631,21 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
       }
     }
   };
-  auto sstore = [&](const Slice& S, int stage) {
+  auto sstore = [&](const Slice& S, int stage, auto os) {
     T (*As)[NSPLIT][BT * LDE] = stage_a(stage);
     T (*Bs)[BT * LDE] = stage_b(stage);
+    if constexpr (AIN) {
 #pragma unroll
-    for (int c = 0; c < NAC; ++c) {
+      for (int s = 0; s < NSPLIT; ++s)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          const int id = tid + c * NTHR;
+          const int r = id / CH, q = id % CH;
+          put(As[0][s] + r * LDE, q, S.rp[s][c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < (AIN ? 0 : NAC); ++c) {
       const int id = tid + c * NTHR;
       const int r = id / CHA, q = id % CHA;
       const int ro = r * LDE;                        // row start, in elements
@@ -589,7 +659,7 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
         };
         if constexpr (!FOLD) {
           put4(0, S.ra[c]);
-        } else if (one_side) {
+        } else if constexpr (decltype(os)::value) {
           put4(side, fold1_f32(S.ra[c], S.rm[c], side ? -1.0f : 1.0f));
         } else {
           u32x4 su, di;
@@ -599,7 +669,7 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
         }
       } else if constexpr (!FOLD) {
         put(As[0][0] + ro, q, S.ra[c]);
-      } else if (one_side) {
+      } else if constexpr (decltype(os)::value) {
         if constexpr (PREC == PREC_F64)
           put(As[side][0] + ro, q, fold1_f64(S.ra[c], S.rm[c], side ? -1.0 : 1.0));
         else
@@ -628,7 +698,7 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
   // differences (1) for odd ones -- uniform per wave, since n/2 and the wave's first column are
   // multiples of WC (the launcher takes WC = 64 only when n/2 is a multiple of 64)
   const int half = n >> 1;
-  const int pa0 = FOLD && col0 + wn >= half ? 1 : 0;
+  const int pa0 = FOLD && !AIN && col0 + wn >= half ? 1 : 0;
   const int KT = K / BK;
   const int r16 = lane & 15;
   auto mfma_slice = [&](int stage) {
@@ -715,33 +785,36 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
     // Two LDS stages and two register sets of fragments.  Step kt issues the MFMAs of slice kt
     // from registers while the fragments of slice kt+1 are read from LDS, slice kt+2 is stored
     // into the stage slice kt came from (read into registers before the previous barrier) and
-    // slice kt+3 is loading from global memory: one barrier per slice, and the matrix cores
-    // never wait for an LDS read.
-    Frag fa0[4], fb0[NB], fa1[4], fb1[NB];
-    gload(sl0, 0);
-    sstore(sl0, 0);
-    if (KT > 1) gload(sl0, BK);
-    __syncthreads();
-    read_frags(0, fa0, fb0);
-    if (KT > 1) {
-      sstore(sl0, 1);
-      if (KT > 2) gload(sl0, 2 * BK);
-    }
-    __syncthreads();
-    auto step = [&](int kt, const Frag (&ca)[4], const Frag (&cb)[NB], Frag (&na)[4],
-                    Frag (&nb)[NB]) {
-      if (kt + 1 < KT) read_frags((kt + 1) & 1, na, nb);
-      if (kt + 2 < KT) {
-        sstore(sl0, kt & 1);
-        if (kt + 3 < KT) gload(sl0, (kt + 3) * BK);
-      }
-      mfma_frags(ca, cb);
+    // slice kt+3 is loading from global memory: one barrier per slice.  A step is one basic
+    // block (the slices past the end re-read the last one and are never used), so that its LDS
+    // and global memory instructions can be issued one between each pair of MFMAs
+    // (interleave_step): the memory work runs under the matrix cores instead of between them.
+    with_side([&](auto os) {
+      Frag fa0[4], fb0[NB], fa1[4], fb1[NB];
+      auto kslice = [&](int k) { return (k < KT ? k : KT - 1) * BK; };
+      gload(sl0, 0);
+      sstore(sl0, 0, os);
+      gload(sl0, kslice(1));
       __syncthreads();
-    };
-    for (int kt = 0; kt < KT; kt += 2) {
-      step(kt, fa0, fb0, fa1, fb1);
-      if (kt + 1 < KT) step(kt + 1, fa1, fb1, fa0, fb0);
-    }
+      read_frags(0, fa0, fb0);
+      sstore(sl0, 1, os);
+      gload(sl0, kslice(2));
+      __syncthreads();
+      auto step = [&](int kt, const Frag (&ca)[4], const Frag (&cb)[NB], Frag (&na)[4],
+                      Frag (&nb)[NB]) {
+        read_frags((kt + 1) & 1, na, nb);
+        sstore(sl0, kt & 1, os);
+        gload(sl0, kslice(kt + 3));
+        mfma_frags(ca, cb);
+        constexpr int NM = KQ * 4 * NB, NR = 2 * (4 + NB);   // MFMAs, 16-byte fragment reads
+        interleave_step<NM, NR, (NM - NR < 24 ? NM - NR : 24)>();
+        __syncthreads();
+      };
+      for (int kt = 0; kt < KT; kt += 2) {
+        step(kt, fa0, fb0, fa1, fb1);
+        if (kt + 1 < KT) step(kt + 1, fa1, fb1, fa0, fb0);
+      }
+    });
   } else if constexpr (lds_stages<PREC, KX>() == 2) {
     // split BF16, 32-wide slices in two LDS stages: the schedule of the FP32/FP64 passes, with
     // the hi/lo fragments of a slice (one 32-wide k-step) double-buffered in registers
@@ -765,56 +838,68 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
         f.blo[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)((const char*)Bs[1] + ro));
       }
     };
+    // each accumulator takes lo*hi, hi*lo, hi*hi in that order; the eight accumulators are
+    // independent, so one kind of product is issued over all of them before the next
     auto mfma_bf = [&](const FragB& f) {
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.alo[a], f.bhi[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ahi[a], f.blo[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ahi[a], f.bhi[b], acc[a][b], 0, 0, 0);
-        }
     };
-    FragB f0, f1;
-    gload(sl0, 0);
-    sstore(sl0, 0);
-    if (KT > 1) gload(sl0, BK);
-    __syncthreads();
-    read_frags_bf(0, f0);
-    if (KT > 1) {
-      sstore(sl0, 1);
-      if (KT > 2) gload(sl0, 2 * BK);
-    }
-    __syncthreads();
-    auto step_bf = [&](int kt, const FragB& cur, FragB& next) {
-      if (kt + 1 < KT) read_frags_bf((kt + 1) & 1, next);
-      if (kt + 2 < KT) {
-        sstore(sl0, kt & 1);
-        if (kt + 3 < KT) gload(sl0, (kt + 3) * BK);
-      }
-      mfma_bf(cur);
+    with_side([&](auto os) {
+      FragB f0, f1;
+      auto kslice = [&](int k) { return (k < KT ? k : KT - 1) * BK; };
+      gload(sl0, 0);
+      sstore(sl0, 0, os);
+      gload(sl0, kslice(1));
       __syncthreads();
-    };
-    for (int kt = 0; kt < KT; kt += 2) {
-      step_bf(kt, f0, f1);
-      if (kt + 1 < KT) step_bf(kt + 1, f1, f0);
-    }
+      read_frags_bf(0, f0);
+      sstore(sl0, 1, os);
+      gload(sl0, kslice(2));
+      __syncthreads();
+      auto step_bf = [&](int kt, const FragB& cur, FragB& next) {
+        read_frags_bf((kt + 1) & 1, next);
+        sstore(sl0, kt & 1, os);
+        gload(sl0, kslice(kt + 3));
+        mfma_bf(cur);
+        interleave_step<24, 12, 12>();
+        __syncthreads();
+      };
+      for (int kt = 0; kt < KT; kt += 2) {
+        step_bf(kt, f0, f1);
+        if (kt + 1 < KT) step_bf(kt + 1, f1, f0);
+      }
+    });
   } else {
     // wide slices: one in flight, its loads cover a whole MFMA phase of twice the length
-    gload(sl0, 0);
-    for (int kt = 0; kt < KT; ++kt) {
-      __syncthreads();
-      sstore(sl0, 0);
-      __syncthreads();
-      if (kt + 1 < KT) gload(sl0, (kt + 1) * BK);
-      mfma_slice(0);
-    }
+    with_side([&](auto os) {
+      gload(sl0, 0);
+      for (int kt = 0; kt < KT; ++kt) {
+        __syncthreads();
+        sstore(sl0, 0, os);
+        __syncthreads();
+        if (kt + 1 < KT) gload(sl0, (kt + 1) * BK);
+        mfma_slice(0);
+      }
+    });
   }
 
-  // epilogue: acc[a][b] holds C[i][j] for the 16 x 16 tile at rows row0 + wm + 16a, columns
-  // col0 + wn + 16b (column l%16 of lane l); the pass stores the transpose, out[j][i].  The tile
-  // goes through LDS (the A staging area) RJ output rows at a time, so that each thread then
-  // finishes and writes a contiguous run of ET elements of one output row.
+  // epilogue: acc[a][b] holds C[i][j] for the 16 x 16 tile at local rows wm + 16a (A row
+  // a_row(.)), columns col0 + wn + 16b (column l%16 of lane l); the pass stores the transpose,
+  // out[j][i].  The tile goes through LDS (the A staging area) RJ output rows at a time, so that
+  // each thread then finishes and writes a contiguous run of ET elements of one output row (or,
+  // folding, EF mirrored pairs of one output row).
   typedef typename std::conditional<PREC == PREC_F64, double, float>::type ST;
   constexpr int RJ = PREC == PREC_F64 ? 16 : 32;              // output rows per round
   constexpr int SS = BT + 16 / (int)sizeof(ST);               // LDS row stride, 16-byte rows
@@ -830,6 +915,11 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
   // output row of accumulator element r: FP32 tiles hold rows 4(l/16) + r, FP64 tiles hold
   // rows (l/16) + 4r (measured lane layouts of the two instructions)
   const int i_base = PREC == PREC_F64 ? (lane >> 4) : 4 * (lane >> 4);
+  // folded output: thread's output row in a round and its first pair (pairs t, HB + t of the
+  // local rows, i.e. A rows row0 + t and n-1-row0-t, fold into element row0 + t of the planes)
+  constexpr int EF = RJ * HB / NTHR;                          // pairs per thread: 2 to 8
+  const int frow = tid / (HB / EF);
+  const int ft = (tid % (HB / EF)) * EF;
   constexpr int i_step = PREC == PREC_F64 ? 4 : 1;
   const int j_l = lane & 15;
   const int orow = tid / (BT / ET);                   // this thread's output row in a round
@@ -877,6 +967,60 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
     }
     __syncthreads();
     if (jr + RJ < BT) fetch(jr + RJ, cur ^ 1);
+    if constexpr (OUT == OUT_FOLD) {
+      // sums (side 0) and differences (side 1) of out[j][i] over mirrored i, in the precision
+      // the next pass would fold in: FP64, else the FP32 values it would have loaded (BF16:
+      // then split into hi, lo)
+      const int jp = col0 + jr + frow;
+      const int j = jp < half ? 2 * jp : 2 * (jp - half) + 1;
+      double x[EF], y[EF];
+#pragma unroll
+      for (int e = 0; e < EF; ++e) {
+        x[e] = (double)stg[frow * SS + ft + e];
+        y[e] = (double)stg[frow * SS + HB + ft + e];
+      }
+      if (E.divide) {
+        const double lj = gld<double>(E.lam + j);
+#pragma unroll
+        for (int e = 0; e < EF; ++e) {
+          x[e] = x[e] / (1.0 + (gld<double>(E.lam + row0 + ft + e) + lj));
+          y[e] = y[e] / (1.0 + (gld<double>(E.lam + n - 1 - row0 - ft - e) + lj));
+        }
+      }
+      T* Cp = (T*)E.C + (int64_t)j * K + row0 + ft;   // plane (0, 0); side s, split p at
+      if constexpr (PREC == PREC_F64) {                 // + (s * NSPLIT + p) * plane
+#pragma unroll
+        for (int e = 0; e < EF; e += 2) {
+          gst<dbl2>(Cp + e, dbl2{x[e] + y[e], x[e + 1] + y[e + 1]});
+          gst<dbl2>(Cp + plane + e, dbl2{x[e] - y[e], x[e + 1] - y[e + 1]});
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < EF; e += 4) {
+          flt4 su, di;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const float xf = (float)x[e + t], yf = (float)y[e + t];
+            su[t] = xf + yf;
+            di[t] = xf - yf;
+          }
+          if constexpr (PREC == PREC_F32) {
+            gst<flt4>(Cp + e, su);
+            gst<flt4>(Cp + plane + e, di);
+          } else {
+            typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+            uint2 hi, lo;
+            split4_bf16(su, &hi, &lo);
+            gst<u32x2>(Cp + e, __builtin_bit_cast(u32x2, hi));
+            gst<u32x2>(Cp + plane + e, __builtin_bit_cast(u32x2, lo));
+            split4_bf16(di, &hi, &lo);
+            gst<u32x2>(Cp + 2 * plane + e, __builtin_bit_cast(u32x2, hi));
+            gst<u32x2>(Cp + 3 * plane + e, __builtin_bit_cast(u32x2, lo));
+          }
+        }
+      }
+      continue;
+    }
     const int jp = col0 + jr + orow;                  // column of the block grid
     const int i0 = row0 + oc;
     if (jp >= n || i0 >= n) continue;                 // n is a multiple of 32: whole runs
@@ -1028,66 +1172,102 @@ bool wide_waves(int64_t n, int tile) {
   return PREC != PREC_BF16 && (tile & kPassWide64) && (!folded(n) || n % 128 == 0);
 }
 
-template <int PREC, int OUT>
+// Prefolded operands: when n/2 is a multiple of the block tile (every block's output columns
+// lie on one side of n/2) the passes exchange their intermediates as folded planes, written by
+// the previous pass's epilogue, unless tile bit kPassPlainA asks for row-major intermediates
+// folded while staging.  Both give bitwise the same results.
+bool prefold(int64_t n, int tile) { return folded(n) && n % (2 * BT) == 0 && !(tile & kPassPlainA); }
+
+// One transform pass.  AIN: the A operand is prefolded planes (1) or row-major (0); OUT_FOLD
+// writes prefolded planes for the next pass.
+template <int PREC, int OUT, int AIN>
 void launch_pass(const Pass2D* d, const Lvl2D* lv, int count, int64_t nmax, int64_t sigma,
                  int tile, hipStream_t st) {
   const unsigned t = (unsigned)((nmax + BT - 1) / BT);
   const dim3 grid(t, t, count);
-  const size_t full = pass_lds_bytes<PREC, 1>(0), fold = pass_lds_bytes<PREC, 1>(1);
-  const size_t wide = pass_lds_bytes<PREC, 2>(1);
-  if constexpr (PREC != PREC_BF16) {
-    if (wide_waves<PREC>(nmax, tile)) {
-      if (!folded(nmax))
-        hipLaunchKernelGGL((k_pass2d<PREC, OUT, 0, 1, 64>), grid, dim3(pass_threads<64>()), full,
-                           st, d, lv, sigma);
-      else
-        hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 1, 64>), grid, dim3(pass_threads<64>()), fold,
-                           st, d, lv, sigma);
-      return;
+  if constexpr (AIN == 1) {
+    const size_t planes = pass_lds_bytes<PREC, 1, 1>(1);
+    if constexpr (PREC != PREC_BF16) {
+      if (tile & kPassWide64) {
+        hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 1, 64, 1>), grid, dim3(pass_threads<64>()),
+                           planes, st, d, lv, sigma);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 1, 32, 1>), grid, dim3(pass_threads<32>()), planes,
+                       st, d, lv, sigma);
+  } else {
+    const size_t full = pass_lds_bytes<PREC, 1, 0>(0), fold = pass_lds_bytes<PREC, 1, 0>(1);
+    const size_t wide = pass_lds_bytes<PREC, 2, 0>(1);
+    if constexpr (PREC != PREC_BF16) {
+      if (wide_waves<PREC>(nmax, tile)) {
+        if constexpr (OUT != OUT_FOLD)
+          if (!folded(nmax)) {
+            hipLaunchKernelGGL((k_pass2d<PREC, OUT, 0, 1, 64, 0>), grid, dim3(pass_threads<64>()),
+                               full, st, d, lv, sigma);
+            return;
+          }
+        hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 1, 64, 0>), grid, dim3(pass_threads<64>()),
+                           fold, st, d, lv, sigma);
+        return;
+      }
+    }
+    if constexpr (OUT != OUT_FOLD)
+      if (!folded(nmax)) {
+        hipLaunchKernelGGL((k_pass2d<PREC, OUT, 0, 1, 32, 0>), grid, dim3(pass_threads<32>()),
+                           full, st, d, lv, sigma);
+        return;
+      }
+    if (!wide_slices<PREC>(nmax) || (tile & kPassNarrowK)) {
+      hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 1, 32, 0>), grid, dim3(pass_threads<32>()), fold,
+                         st, d, lv, sigma);
+    } else {
+      if constexpr (PREC == PREC_BF16)
+        hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 2, 32, 0>), grid, dim3(pass_threads<32>()),
+                           wide, st, d, lv, sigma);
     }
   }
-  if (!folded(nmax)) {
-    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 0, 1, 32>), grid, dim3(pass_threads<32>()), full, st,
-                       d, lv, sigma);
-  } else if (!wide_slices<PREC>(nmax) || (tile & kPassNarrowK)) {
-    hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 1, 32>), grid, dim3(pass_threads<32>()), fold, st,
-                       d, lv, sigma);
-  } else {
-    if constexpr (PREC == PREC_BF16)
-      hipLaunchKernelGGL((k_pass2d<PREC, OUT, 1, 2, 32>), grid, dim3(pass_threads<32>()), wide,
-                         st, d, lv, sigma);
-  }
 }
 
-// Allow the pass variants their LDS (host call, outside any stream capture).
-template <int PREC, int OUT, int FOLD, int KX>
+// Allow a pass variant its LDS (host call, outside any stream capture).
+template <int PREC, int OUT, int FOLD, int KX, int WC, int AIN>
+hipError_t allow_one() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass2d<PREC, OUT, FOLD, KX, WC, AIN>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)pass_lds_bytes<PREC, KX, AIN>(FOLD));
+}
+// every variant launch_pass<PREC, OUT, AIN> can launch
+template <int PREC, int OUT, int AIN>
 hipError_t allow_lds() {
-  hipError_t e = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&k_pass2d<PREC, OUT, FOLD, KX, 32>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, (int)pass_lds_bytes<PREC, KX>(FOLD));
-  if constexpr (PREC != PREC_BF16 && KX == 1)
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass2d<PREC, OUT, FOLD, KX, 64>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)pass_lds_bytes<PREC, KX>(FOLD));
-  return e;
-}
-
-// every variant a precision launches: its own output type and the final update, folded or not
-// (and, split BF16, with wide slices)
-template <int PREC, int OUT>
-hipError_t allow_out() {
-  hipError_t e = allow_lds<PREC, OUT, 0, 1>();
-  if (e == hipSuccess) e = allow_lds<PREC, OUT, 1, 1>();
-  if constexpr (PREC == PREC_BF16)
-    if (e == hipSuccess) e = allow_lds<PREC, OUT, 1, 2>();
+  hipError_t e = hipSuccess;
+  auto add = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  if constexpr (AIN == 1) {
+    add(allow_one<PREC, OUT, 1, 1, 32, 1>());
+    if constexpr (PREC != PREC_BF16) add(allow_one<PREC, OUT, 1, 1, 64, 1>());
+  } else {
+    if constexpr (OUT != OUT_FOLD) add(allow_one<PREC, OUT, 0, 1, 32, 0>());
+    add(allow_one<PREC, OUT, 1, 1, 32, 0>());
+    if constexpr (PREC == PREC_BF16) {
+      add(allow_one<PREC, OUT, 1, 2, 32, 0>());
+    } else {
+      if constexpr (OUT != OUT_FOLD) add(allow_one<PREC, OUT, 0, 1, 64, 0>());
+      add(allow_one<PREC, OUT, 1, 1, 64, 0>());
+    }
+  }
   return e;
 }
 template <int PREC>
 hipError_t allow_pass() {
   constexpr int OWN = PREC == PREC_F64 ? OUT_F64 : OUT_F32;
-  hipError_t e = allow_out<PREC, OWN>();
-  if (e == hipSuccess) e = allow_out<PREC, OUT_FINAL>();
+  hipError_t e = allow_lds<PREC, OWN, 0>();
+  if (e == hipSuccess) e = allow_lds<PREC, OUT_FINAL, 0>();
+  if (e == hipSuccess) e = allow_lds<PREC, OUT_FOLD, 0>();
+  if (e == hipSuccess) e = allow_lds<PREC, OUT_FOLD, 1>();
+  if (e == hipSuccess) e = allow_lds<PREC, OUT_FINAL, 1>();
+  if constexpr (PREC != PREC_F64)
+    if (e == hipSuccess) e = allow_lds<PREC, OUT_F32, 1>();
   return e;
 }
 
@@ -1236,6 +1416,10 @@ void plan2d_tile_candidates(const Plan2D* pl, std::vector<int>* out) {
   out->push_back(0);
   if (pl->prec != PREC_BF16 && (!folded(pl->n) || pl->n % 128 == 0)) out->push_back(kPassWide64);
   if (pl->prec == PREC_BF16 && wide_slices<PREC_BF16>(pl->n)) out->push_back(kPassNarrowK);
+  if (prefold(pl->n, 0)) {
+    const size_t c = out->size();
+    for (size_t i = 0; i < c; ++i) out->push_back((*out)[i] | kPassPlainA);
+  }
 }
 
 int plan2d_set_tile(Plan2D* pl, int tile) {
@@ -1259,6 +1443,25 @@ int plan2d_arm(Plan2D* pl, int64_t nt, hipStream_t stream) {
 
 namespace {
 
+// The four passes of one solve (passes d[0 .. 3 cnt)): the last writes LAST.  With prefolded
+// operands the first three write folded planes and the later three read them.
+template <int PREC, int LAST>
+void run_solve(const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nmax, int64_t s, int tile,
+               hipStream_t st) {
+  constexpr int OWN = PREC == PREC_F64 ? OUT_F64 : OUT_F32;
+  if (prefold(nmax, tile)) {
+    launch_pass<PREC, OUT_FOLD, 0>(d + 0 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC, OUT_FOLD, 1>(d + 1 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC, OUT_FOLD, 1>(d + 2 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC, LAST, 1>(d + 3 * cnt, lv, cnt, nmax, s, tile, st);
+  } else {
+    launch_pass<PREC, OWN, 0>(d + 0 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC, OWN, 0>(d + 1 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC, OWN, 0>(d + 2 * cnt, lv, cnt, nmax, s, tile, st);
+    launch_pass<PREC, LAST, 0>(d + 3 * cnt, lv, cnt, nmax, s, tile, st);
+  }
+}
+
 // Every stage of one pipeline step for `cnt` (plan, level) entries of one precision: the
 // right-hand side, the transform passes and (reduced precision) the residual, one launch each.
 // passes is pass-major: passes[k * cnt + e].
@@ -1266,30 +1469,15 @@ void run_stages(int prec, const Lvl2D* lv, const Pass2D* d, int cnt, int64_t nma
                 int tile, hipStream_t st) {
   launch_stencil(k_rhs2d, lv, cnt, nmax, s, st);
   if (prec == PREC_F64) {
-    launch_pass<PREC_F64, OUT_F64>(d + 0 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_F64, OUT_F64>(d + 1 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_F64, OUT_F64>(d + 2 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_F64, OUT_FINAL>(d + 3 * cnt, lv, cnt, nmax, s, tile, st);
+    run_solve<PREC_F64, OUT_FINAL>(lv, d, cnt, nmax, s, tile, st);
   } else if (prec == PREC_F32) {
-    launch_pass<PREC_F32, OUT_F32>(d + 0 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 3 * cnt, lv, cnt, nmax, s, tile, st);
+    run_solve<PREC_F32, OUT_F32>(lv, d, cnt, nmax, s, tile, st);
     launch_stencil(k_resid2d, lv, cnt, nmax, s, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_F32, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_F32, OUT_FINAL>(d + 7 * cnt, lv, cnt, nmax, s, tile, st);
+    run_solve<PREC_F32, OUT_FINAL>(lv, d + 4 * cnt, cnt, nmax, s, tile, st);
   } else {
-    launch_pass<PREC_BF16, OUT_F32>(d + 0 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 1 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 2 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 3 * cnt, lv, cnt, nmax, s, tile, st);
+    run_solve<PREC_BF16, OUT_F32>(lv, d, cnt, nmax, s, tile, st);
     launch_stencil(k_resid2d, lv, cnt, nmax, s, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 4 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 5 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_BF16, OUT_F32>(d + 6 * cnt, lv, cnt, nmax, s, tile, st);
-    launch_pass<PREC_BF16, OUT_FINAL>(d + 7 * cnt, lv, cnt, nmax, s, tile, st);
+    run_solve<PREC_BF16, OUT_FINAL>(lv, d + 4 * cnt, cnt, nmax, s, tile, st);
   }
 }
 
@@ -1440,23 +1628,34 @@ int plan2d_advance(Plan2D* const* pls, int count, const int64_t* sigma_before, i
 int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us) {
   const int P = pl->P;
   const int64_t n = pl->n;
-  // inputs of the first pass of this step, then `reps` back-to-back launches of that pass
+  const int tile = pl->tile;
+  const bool pf = prefold(n, tile);
+  // inputs of the second pass of this step (the right-hand side and the first pass), then
+  // `reps` back-to-back launches of the second pass, which only rewrites an intermediate
   launch_stencil(k_rhs2d, pl->d_levels, P, n, sigma, stream);
+  auto pass = [&](int k) {
+    const Pass2D* d = pl->d_passes + k * P;
+    if (pl->prec == PREC_F64) {
+      if (pf && k == 0) launch_pass<PREC_F64, OUT_FOLD, 0>(d, pl->d_levels, P, n, sigma, tile, stream);
+      else if (pf) launch_pass<PREC_F64, OUT_FOLD, 1>(d, pl->d_levels, P, n, sigma, tile, stream);
+      else launch_pass<PREC_F64, OUT_F64, 0>(d, pl->d_levels, P, n, sigma, tile, stream);
+    } else if (pl->prec == PREC_F32) {
+      if (pf && k == 0) launch_pass<PREC_F32, OUT_FOLD, 0>(d, pl->d_levels, P, n, sigma, tile, stream);
+      else if (pf) launch_pass<PREC_F32, OUT_FOLD, 1>(d, pl->d_levels, P, n, sigma, tile, stream);
+      else launch_pass<PREC_F32, OUT_F32, 0>(d, pl->d_levels, P, n, sigma, tile, stream);
+    } else {
+      if (pf && k == 0) launch_pass<PREC_BF16, OUT_FOLD, 0>(d, pl->d_levels, P, n, sigma, tile, stream);
+      else if (pf) launch_pass<PREC_BF16, OUT_FOLD, 1>(d, pl->d_levels, P, n, sigma, tile, stream);
+      else launch_pass<PREC_BF16, OUT_F32, 0>(d, pl->d_levels, P, n, sigma, tile, stream);
+    }
+  };
+  pass(0);
   hipEvent_t a, b;
   RIDC_HIP_TRY(hipEventCreate(&a));
   RIDC_HIP_TRY(hipEventCreate(&b));
-  auto one = [&]() {
-    if (pl->prec == PREC_F64)
-      launch_pass<PREC_F64, OUT_F64>(pl->d_passes, pl->d_levels, P, n, sigma, pl->tile, stream);
-    else if (pl->prec == PREC_F32)
-      launch_pass<PREC_F32, OUT_F32>(pl->d_passes, pl->d_levels, P, n, sigma, pl->tile, stream);
-    else
-      launch_pass<PREC_BF16, OUT_F32>(pl->d_passes, pl->d_levels, P, n, sigma, pl->tile,
-                                      stream);
-  };
-  one();
+  pass(1);
   (void)hipEventRecord(a, stream);
-  for (int r = 0; r < reps; ++r) one();
+  for (int r = 0; r < reps; ++r) pass(1);
   (void)hipEventRecord(b, stream);
   hipError_t e = hipEventSynchronize(b);
   float ms = 0;

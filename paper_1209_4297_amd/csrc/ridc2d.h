@@ -27,16 +27,19 @@ void plan2d_cost(const Plan2D* pl, double* bytes, double* flops);
 // Launch shape of the transform passes (bits; every shape gives bitwise the same results):
 // kPassWide64 = 64-column waves, 4 per block (FP32/FP64 passes, n/2 a multiple of 64 or no
 // fold); kPassNarrowK = 32-wide k-slices in two LDS stages (split-BF16 pass, instead of 64-wide
-// slices in one).
+// slices in one); kPassPlainA = row-major intermediates folded while staging, instead of the
+// folded planes the passes otherwise exchange when n is a multiple of 256.
 constexpr int kPassWide64 = 1;
 constexpr int kPassNarrowK = 2;
+constexpr int kPassPlainA = 4;
 int plan2d_tile(const Plan2D* pl);
 // The shapes this plan's side and precision allow (0, the default, first).
 void plan2d_tile_candidates(const Plan2D* pl, std::vector<int>* out);
 // Errors: RIDC_E_INVAL for a shape the plan does not allow.
 int plan2d_set_tile(Plan2D* pl, int tile);
-// Average duration (us) of `reps` back-to-back launches of the first transform pass of step
-// `sigma` (every level active), after computing that step's right-hand side once.
+// Average duration (us) of `reps` back-to-back launches of the second transform pass of step
+// `sigma` (every level active; the kind of most passes of a step), after computing that step's
+// right-hand side and first pass once.
 int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us);
 // Average duration (us) of `reps` back-to-back launches of the right-hand-side kernel of step
 // `sigma` (every level active) and its algorithmic HBM bytes per launch.

@@ -1,5 +1,9 @@
 """The autotuners' launch shapes: every 2D transform-pass shape gives bitwise the same
-integration, and ridc_autotune records its choice in the tuning table (saved as JSON)."""
+integration, and ridc_autotune records its choice in the tuning table (saved as JSON).
+
+Shape bits: 1 = 64-column waves (FP32/FP64), 2 = 32-wide k-slices (split BF16), 4 = row-major
+intermediates folded while staging instead of the prefolded planes (sides that are multiples
+of 256)."""
 import json
 import sys
 
@@ -28,8 +32,8 @@ def _run(env, prob, u0, prec, flags):
     return out
 
 
-@pytest.mark.parametrize("prec,shapes", [("fp64", [0, 1]), ("fp32", [0, 1]),
-                                         ("bf16x3", [0, 2])])
+@pytest.mark.parametrize("prec,shapes", [("fp64", [0, 1, 4, 5]), ("fp32", [0, 1, 4, 5]),
+                                         ("bf16x3", [0, 2, 4, 6])])
 @pytest.mark.parametrize("n", [256, 512])
 def test_pass_shapes_are_bitwise_equal(env, prec, shapes, n):
     prob, u0 = workloads.config_reacdiff_2d(n=n, nt=12, order=4, T=0.024)
@@ -47,6 +51,8 @@ def test_unavailable_shape_is_rejected(env):
         s.set_tile(0, 0, 1)        # n = 192: 64-column waves would split the fold
     with pytest.raises(ridc.RidcError):
         s.set_tile(0, 0, 2)        # 32-wide slices are a split-BF16 shape
+    with pytest.raises(ridc.RidcError):
+        s.set_tile(0, 0, 4)        # n = 192: no prefolded planes, so no choice of them
     s.close()
 
 
@@ -56,7 +62,7 @@ def test_autotune_records_the_2d_shape(env, tmp_path):
     ridc.tune_clear()
     s = ridc.Ridc(prob, prec="bf16x3")
     threads, rows, flags = s.autotune()
-    assert flags in (0, 2) and rows == 0 and threads == 512
+    assert flags in (0, 2, 4, 6) and rows == 0 and threads == 512
     x0 = torch.tensor(u0.reshape(-1), device="cuda")
     out = s.integrate(x0, prob["nt"]).cpu().numpy()        # re-armed by integrate
     s.close()
