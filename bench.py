@@ -48,12 +48,16 @@ MEASURED_TRAFFIC = {
     ("reacdiff1d", (1024, 128, 0)): ("1d", "564458ee427cc4d1", 4530176),
     ("batched1d", (256, 1536)): ("1d", "564458ee427cc4d1", 72678016),
     ("batched1d", (512, 1536)): ("1d", "564458ee427cc4d1", 72604672),
-    ("reacdiff2d_rhs", "fp64"): ("2d", "f665aa3c456117d7", 185794055),
-    ("reacdiff2d", "fp64"): ("2d", "f665aa3c456117d7", 100917722),
-    ("reacdiff2d_rhs", "fp32"): ("2d", "f665aa3c456117d7", 202970027),
-    ("reacdiff2d", "fp32"): ("2d", "f665aa3c456117d7", 50584031),
-    ("reacdiff2d_rhs", "bf16x3"): ("2d", "f665aa3c456117d7", 202870307),
-    ("reacdiff2d", "bf16x3"): ("2d", "f665aa3c456117d7", 50570802),
+    ("reacdiff2d_rhs", "fp64"): ("2d", "a717547b06f5144b", 185666944),
+    ("reacdiff2d_rhs", "fp32"): ("2d", "a717547b06f5144b", 202917632),
+    ("reacdiff2d_rhs", "bf16x3"): ("2d", "a717547b06f5144b", 202824960),
+    # the timed transform pass (the second of a step) per (precision, pass-shape bits)
+    ("reacdiff2d", ("fp64", 0)): ("2d", "a717547b06f5144b", 100881664),
+    ("reacdiff2d", ("fp64", 4)): ("2d", "a717547b06f5144b", 100904192),
+    ("reacdiff2d", ("fp32", 0)): ("2d", "a717547b06f5144b", 50555648),
+    ("reacdiff2d", ("fp32", 4)): ("2d", "a717547b06f5144b", 50574080),
+    ("reacdiff2d", ("bf16x3", 0)): ("2d", "a717547b06f5144b", 50556672),
+    ("reacdiff2d", ("bf16x3", 4)): ("2d", "a717547b06f5144b", 50563840),
 }
 
 
@@ -115,6 +119,10 @@ def parse():
                     help="override the number of time steps (short runs for counter profiling)")
     ap.add_argument("--tile", default=None,
                     help="1D tiling 'threads,rows,flags' instead of autotuning (rows 0 = whole cycle)")
+    ap.add_argument("--pass-shape", type=int, default=None, metavar="BITS",
+                    help="2D: transform-pass shape bits (1: 64-column waves, 2: 32-wide split-BF16 "
+                         "slices, 4: row-major intermediates instead of prefolded planes) instead "
+                         "of autotuning")
     ap.add_argument("--batch-tile", default=None,
                     help="batched 1D: grouped-launch tiling 'threads,rows' instead of autotuning "
                          "(rows 0 = whole cycles)")
@@ -156,6 +164,9 @@ def run_single(args, torch, ridc, prob, u0, prec, steps, warmup, tune=True, segm
         tile = tuple(int(x) for x in args.tile.split(",")) + (0,)
         tile = tile[:3]
         s.set_tile(*tile)
+    elif prob["dim"] == 2 and args.pass_shape is not None:
+        s.set_tile(0, 0, args.pass_shape)
+        tile = (256 if args.pass_shape & 1 else 512, 0, args.pass_shape)
     elif tune:
         tile = s.autotune()     # 1D tiling, or the 2D transform-pass shape (cached per n, prec)
     x0 = torch.tensor(np.asarray(u0).reshape(-1), dtype=torch.float64, device="cuda")
@@ -409,8 +420,10 @@ def shape_name(shape):
     if shape is None:
         return None
     bits = shape[2]
-    return {"threads": shape[0], "wave_columns": 64 if bits & 1 else 32,
-            "k_slice": "32 (two LDS stages)" if bits & 2 else "default"}
+    return {"bits": bits, "threads": shape[0], "wave_columns": 64 if bits & 1 else 32,
+            "k_slice": "32 (two LDS stages)" if bits & 2 else "default",
+            "intermediates": "row-major, folded while staging" if bits & 4
+            else "prefolded planes (n a multiple of 256)"}
 
 
 def stencil_roofline(ridc, s, x0, nt, reps):
@@ -445,7 +458,7 @@ def bench_2d(args, torch, ridc):
     roof["pass_shape"] = shape_name(shape)
     roof_rhs = stencil_roofline(ridc, s, x0, nt, reps)
     if args.nt is None:
-        roof["traffic"] = measured_traffic("reacdiff2d", args.prec)
+        roof["traffic"] = measured_traffic("reacdiff2d", (args.prec, shape[2] if shape else 0))
         roof_rhs["traffic"] = measured_traffic("reacdiff2d_rhs", args.prec)
     s.close()
     check = {}
@@ -481,6 +494,9 @@ def bench_2d(args, torch, ridc):
                                                          steps, warmup)
                 roof_m = roofline_single(ridc, sm, x0, nt, reps, "mfma", prec)
                 roof_m["pass_shape"] = shape_name(shape_m)
+                if args.nt is None:
+                    roof_m["traffic"] = measured_traffic("reacdiff2d",
+                                                         (prec, shape_m[2] if shape_m else 0))
                 sm.close()
                 dist = float(np.linalg.norm(out_m - u64) / np.linalg.norm(u64))
                 matched[prec] = {
@@ -492,7 +508,7 @@ def bench_2d(args, torch, ridc):
                     "rel_l2_vs_fp64": dist, "err_disc": err_disc,
                     "matched": bool(dist <= 0.1 * err_disc),
                     "roofline": {k: roof_m[k] for k in ("bound", "achieved", "peak", "unit",
-                                                        "frac", "kernel", "launch_us",
+                                                        "frac", "traffic", "kernel", "launch_us",
                                                         "flops_per_launch", "pass_shape")}}
     cpu = None
     if not args.no_cpu:
