@@ -659,9 +659,9 @@ def bench_serving(args, torch, ridc):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: every box here has a single MI355X, and this "
-              "build measures the one-GPU hot path (see DESIGN.md for how it would shard).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): the hot path runs on a single MI355X; "
+              "independent instances and requests would shard one process per GPU with no "
+              "exchange between them.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1209_4297_amd import ridc
