@@ -19,8 +19,11 @@
 // v_mfma_f32_16x16x32_bf16 products of hi/lo BF16 splits), batched over every active level of
 // every instance in one launch; the eigenvalue divide and the final update are fused into the
 // epilogues of passes 2 and 4.  Sides that are multiples of 64 fold Q by its reflection
-// symmetry, Q_{n-1-k, j} = (-1)^j Q_{k, j}, which halves the contraction (k_pass2d).  The
-// split-BF16 path keeps its intermediates in FP32 and splits its operand while staging it.
+// symmetry, Q_{n-1-k, j} = (-1)^j Q_{k, j}, which halves the contraction (k_pass2d).  When n is
+// a multiple of 256 the passes of a solve hand each other their intermediates already folded
+// (sums and differences of mirrored columns; split into BF16 hi/lo on the split-BF16 path);
+// otherwise, and for the first pass of a solve, the intermediates are row-major (FP32 on the
+// reduced-precision paths) and a pass folds (and splits) its operand while staging it.
 //
 // Reduced precision (FP32 or split BF16) adds one FP64 residual refinement:
 //   x1 = S~(b),  rho = b - (x1 - dt nu Lap_h x1)  (FP64 5-point),  x = x1 + S~(rho);
@@ -54,7 +57,8 @@ struct Lvl2D {
   const double* W;      // weights, j rows x (j+1)
   double* b64;          // FP64 right-hand side (kept for the residual)
   double* x64;          // FP64 first solve (refinement) or FP64 intermediate
-  void* lo0;            // FP32 buffers of the reduced-precision paths
+  void* lo0;            // FP32-sized buffers of the reduced-precision paths (row-major FP32 or
+                        // folded planes)
   void* lo1;
   int64_t nt, sigma0;
   int32_t n, j, R_own, R_prev, fe, prec;
@@ -63,7 +67,8 @@ struct Lvl2D {
 
 // One batch entry of a transform pass.
 struct Pass2D {
-  const void* A;        // input, row-major n x n (FP64, or FP32 in the reduced-precision paths)
+  const void* A;        // input: row-major n x n (FP64, or FP32 in the reduced-precision paths),
+                        // or the folded planes of the previous pass
   void* C;              // output (unless final)
   const float* add;     // final epilogue: extra term (x1 of the refinement, FP32), nullable
   const void* Q;        // transform matrix in the input precision (BF16: hi, lo at +n*n)
@@ -119,8 +124,8 @@ __device__ __forceinline__ void gst(void* p, V v) {
   *(__attribute__((address_space(1))) V*)p = v;
 }
 
-// The reduced-precision paths keep their intermediates in FP32; the split-BF16 pass splits its
-// A operand into BF16 (hi, lo) while staging it.
+// The FP32 copy of a right-hand side or residual that the first pass of a reduced-precision
+// solve reads (row-major; that pass folds it, and the split-BF16 pass splits it, while staging).
 __device__ __forceinline__ void store_lo(void* base, int64_t idx, double v) {
   gst<float>((float*)base + idx, (float)v);
 }
@@ -528,7 +533,8 @@ __global__ __launch_bounds__(pass_threads<WC>()) void k_pass2d(const Pass2D* __r
   if ((MIRROR ? 2 * row0 : row0) >= n || col0 >= n) return;
   auto a_row = [&](int r) { return MIRROR ? (r < HB ? row0 + r : n - 1 - row0 - (r - HB)) : row0 + r; };
   const int64_t nn = (int64_t)n * n;
-  // A arrives in FP64 or FP32 (the split-BF16 pass splits it while staging); Q in T
+  // A arrives row-major in FP64 or FP32 (the split-BF16 pass splits it while staging), or as
+  // prefolded planes of T (AIN); Q in T
   typedef typename std::conditional<PREC == PREC_BF16, float, T>::type TA;
   constexpr int EA = 16 / (int)sizeof(TA);          // A elements per 16-byte chunk
   constexpr int CHA = BK * (int)sizeof(TA) / 16;    // A chunks per row
