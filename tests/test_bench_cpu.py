@@ -30,14 +30,21 @@ def test_method_step_bytes_by_level_sum(bench):
 
 
 def test_traffic_table_is_tied_to_source_hashes(bench):
-    import hashlib
     for key, (src, sha, nbytes) in bench.MEASURED_TRAFFIC.items():
         assert src in bench.KERNEL_SOURCE
         assert len(sha) == 16 and nbytes > 0
-        with open(bench.KERNEL_SOURCE[src], "rb") as f:
-            current = hashlib.sha256(f.read()).hexdigest()[:16]
+        current = bench.code_hash(bench.KERNEL_SOURCE[src])
         expect = nbytes if current == sha else None
         assert bench.measured_traffic(*key) == expect
+
+
+def test_code_hash_ignores_comments_and_blank_space_only(bench, tmp_path):
+    a, b, c = tmp_path / "a.hip", tmp_path / "b.hip", tmp_path / "c.hip"
+    a.write_text("int f(int x) {\n  return x + 1;  // one\n}\n")
+    b.write_text("/* doc */ int f(int x)\n{ return x + 1; }\n// trailing\n")
+    c.write_text("int f(int x) {\n  return x + 2;\n}\n")
+    assert bench.code_hash(str(a)) == bench.code_hash(str(b))
+    assert bench.code_hash(str(a)) != bench.code_hash(str(c))
 
 
 def test_more_than_one_gpu_is_refused():
