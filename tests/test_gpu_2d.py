@@ -67,9 +67,11 @@ def oracle2d(prob, u0, nt=None):
     return ridc_pipelined(Problem.from_dict(prob), u0, nt, prob["order"])
 
 
+# n = 256 and 768 (multiples of 256) run the passes that exchange prefolded planes; 768 also
+# has a contraction (n/2 = 384) that is not a power of two
 @pytest.mark.parametrize("n,nt,order", [(64, 40, 4), (96, 30, 4), (256, 20, 4), (160, 12, 3),
                                         (32, 8, 1), (64, 6, 6), (32, 20, 8),
-                                        (192, 10, 4)])
+                                        (192, 10, 4), (768, 6, 4)])
 def test_fp64_parity(env, n, nt, order):
     prob, u0 = workloads.config_reacdiff_2d(n=n, nt=nt, order=order, T=nt * 2e-3, nu=1e-3)
     _say(f"case: 2D fp64 n={n} nt={nt} P={order}")
@@ -83,7 +85,7 @@ def test_fp64_parity(env, n, nt, order):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("n,nt", [(128, 40), (96, 20), (192, 10)])
+@pytest.mark.parametrize("n,nt", [(128, 40), (96, 20), (192, 10), (256, 12), (768, 6)])
 def test_mixed_precision_parity(env, prec, n, nt):
     prob, u0 = workloads.config_reacdiff_2d(n=n, nt=nt, order=4, T=nt * 2e-3, nu=1e-3)
     _say(f"case: 2D {prec} n={n} nt={nt}")

@@ -34,7 +34,7 @@ def _run(env, prob, u0, prec, flags):
 
 @pytest.mark.parametrize("prec,shapes", [("fp64", [0, 1, 4, 5]), ("fp32", [0, 1, 4, 5]),
                                          ("bf16x3", [0, 2, 4, 6])])
-@pytest.mark.parametrize("n", [256, 512])
+@pytest.mark.parametrize("n", [256, 512, 768])
 def test_pass_shapes_are_bitwise_equal(env, prec, shapes, n):
     prob, u0 = workloads.config_reacdiff_2d(n=n, nt=12, order=4, T=0.024)
     print(f"case: 2D n={n} {prec} shapes {shapes}", flush=True)
