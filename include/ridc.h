@@ -306,7 +306,10 @@ int ridc_tune_clear(void);
  *    same values; the handle does not advance);
  *  - 1D, whole-integration workgroup (systems that fit one CU's LDS): one launch running
  *    `reps` steps; the handle runs ahead and is left unarmed (call ridc_begin again);
- *  - 2D: `reps` launches of the first transform pass over all levels.
+ *  - 2D: `reps` launches of the second transform pass of that step over all levels (after its
+ *    right-hand side and first pass once): the kind of most of a step's passes.  These launches
+ *    rewrite only per-step intermediates (the right-hand side and transform buffers, which the
+ *    step recomputes); the level rings and the handle's position are unchanged.
  * *work_per_launch (nullable) receives the algorithmic HBM bytes (1D, per step) or flops (2D,
  * per pass).  Errors: RIDC_E_STATE if the next step is not a full one or too few remain.     */
 int ridc_kernel_time(ridc_handle* h, int32_t reps, double* us_per_launch,
