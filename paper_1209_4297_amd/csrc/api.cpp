@@ -933,7 +933,7 @@ int advance_imex(const std::vector<ridc_handle*>& hs, int64_t max_steps, hipStre
 }
 
 // 2D: the transform-pass shape of the handle's (n, precision), from the tuning table or
-// measured: every shape the plan allows times `reps` launches of the first pass of a step with
+// measured: every shape the plan allows times `reps` launches of the second pass of a step with
 // every level active (on zeroed rings), the fastest is kept and recorded.  Leaves the handle
 // unarmed.  Outputs: threads per block of the chosen shape, 0, and the shape bits.
 int autotune_2d(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out) {
