@@ -157,10 +157,26 @@ __device__ __forceinline__ float lane_above(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
 
+// The block a workgroup runs: column strip bx, block row by, level bz.  Workgroups go to the 8
+// XCDs round-robin by linear id.  When the block rows of all levels (grid y times z) are a
+// multiple of 8, block row R = 8k + x runs whole on XCD x, so the strips beside a block, whose
+// edge columns it reads, sit in the same L2; the levels still spread over every XCD.
+struct StBlock {
+  unsigned x, y, z;
+};
+__device__ __forceinline__ StBlock stencil_block() {
+  const unsigned gx = gridDim.x, rows = gridDim.y * gridDim.z;
+  if (rows % 8 != 0) return StBlock{blockIdx.x, blockIdx.y, blockIdx.z};
+  const unsigned id = blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned r = id / 8;
+  const unsigned row = (r / gx) * 8 + id % 8;
+  return StBlock{r % gx, row % gridDim.y, row / gridDim.y};
+}
+
 // Where a block's wave sits: the first row and column it owns, or false when it owns none.
-__device__ __forceinline__ bool stencil_tile(int n, int* iy0, int* ix0) {
-  *ix0 = blockIdx.x * 64;
-  *iy0 = (blockIdx.y * ST_WAVES + (threadIdx.x >> 6)) * ST_RY;
+__device__ __forceinline__ bool stencil_tile(int n, const StBlock& b, int* iy0, int* ix0) {
+  *ix0 = (int)b.x * 64;
+  *iy0 = ((int)b.y * ST_WAVES + (int)(threadIdx.x >> 6)) * ST_RY;
   return *ix0 < n && *iy0 < n;
 }
 
@@ -278,11 +294,12 @@ __device__ __forceinline__ void rhs_level(const Lvl2D& L, int64_t m, int iy0, in
 }
 
 __global__ __launch_bounds__(256) void k_rhs2d(const Lvl2D* __restrict__ levels, int64_t sigma) {
-  const Lvl2D& L = levels[blockIdx.z];
+  const StBlock blk = stencil_block();
+  const Lvl2D& L = levels[blk.z];
   int64_t m;
   if (!level_active(L, sigma, &m)) return;
   int iy0, ix0;
-  if (!stencil_tile(L.n, &iy0, &ix0)) return;
+  if (!stencil_tile(L.n, blk, &iy0, &ix0)) return;
   switch (L.j) {
     case 0: rhs_level<0>(L, m, iy0, ix0); break;
     case 1: rhs_level<2>(L, m, iy0, ix0); break;
@@ -297,12 +314,13 @@ __global__ __launch_bounds__(256) void k_rhs2d(const Lvl2D* __restrict__ levels,
 // wave's column strip is loaded before any is used, so all of a wave's loads are in flight at
 // once.
 __global__ __launch_bounds__(256) void k_resid2d(const Lvl2D* __restrict__ levels, int64_t sigma) {
-  const Lvl2D& L = levels[blockIdx.z];
+  const StBlock blk = stencil_block();
+  const Lvl2D& L = levels[blk.z];
   int64_t m;
   if (!level_active(L, sigma, &m)) return;
   const int n = L.n;
   int iy0, ix0;
-  if (!stencil_tile(n, &iy0, &ix0)) return;
+  if (!stencil_tile(n, blk, &iy0, &ix0)) return;
   const int lane = threadIdx.x & 63;
   const int ix = ix0 + lane;
   const bool col = ix < n;
