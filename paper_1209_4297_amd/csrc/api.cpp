@@ -933,9 +933,10 @@ int advance_imex(const std::vector<ridc_handle*>& hs, int64_t max_steps, hipStre
 }
 
 // 2D: the transform-pass shape of the handle's (n, precision), from the tuning table or
-// measured: every shape the plan allows times `reps` launches of the second pass of a step with
-// every level active (on zeroed rings), the fastest is kept and recorded.  Leaves the handle
-// unarmed.  Outputs: threads per block of the chosen shape, 0, and the shape bits.
+// measured: every shape the plan allows times 10 runs of a whole step with every level active
+// (on zeroed rings; a shape can change the first pass of a solve and the later ones
+// differently), the fastest is kept and recorded.  Leaves the handle unarmed.  Outputs:
+// threads per block of the chosen shape, 0, and the shape bits.
 int autotune_2d(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out) {
   Plan2D* pl = h->p2;
   const int prec = h->p.prec;
@@ -957,7 +958,7 @@ int autotune_2d(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t
         rc = plan2d_set_tile(pl, c);
         if (rc != RIDC_OK) return rc;
         double us = 0;
-        rc = plan2d_time_pass(pl, s, 20, h->stream, &us);
+        rc = plan2d_time_step(pl, s, 10, h->stream, &us);
         if (rc != RIDC_OK) return rc;
         if (us < best) {
           best = us;
