@@ -933,10 +933,34 @@ int advance_imex(const std::vector<ridc_handle*>& hs, int64_t max_steps, hipStre
 }
 
 // 2D: the transform-pass shape of the handle's (n, precision), from the tuning table or
-// measured: every shape the plan allows times 10 runs of a whole step with every level active
-// (on zeroed rings; a shape can change the first pass of a solve and the later ones
-// differently), the fastest is kept and recorded.  Leaves the handle unarmed.  Outputs:
+// measured: every shape the plan allows times 10 whole steps with every level active (on zeroed
+// rings; a shape can change the first pass of a solve and the later ones differently), the
+// fastest is kept and recorded.  Leaves the handle unarmed.  Outputs:
 // threads per block of the chosen shape, 0, and the shape bits.
+// Average duration (us) of `reps` consecutive whole steps (every stage) of one plan from step s.
+int time_2d_steps(Plan2D* pl, int64_t s, int reps, hipStream_t stream, double* us) {
+  Plan2D* pls[1] = {pl};
+  int64_t before = s - 1;
+  int rc = plan2d_advance(pls, 1, &before, 1, stream);       // warm
+  if (rc != RIDC_OK) return rc;
+  hipEvent_t a, b;
+  RIDC_HIP_TRY(hipEventCreate(&a));
+  RIDC_HIP_TRY(hipEventCreate(&b));
+  before = s;
+  (void)hipEventRecord(a, stream);
+  rc = plan2d_advance(pls, 1, &before, reps, stream);
+  (void)hipEventRecord(b, stream);
+  hipError_t e = hipEventSynchronize(b);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc != RIDC_OK) return rc;
+  if (e != hipSuccess) return fail(RIDC_E_HIP, std::string("step timing: ") + hipGetErrorString(e));
+  *us = 1e3 * (double)ms / reps;
+  return RIDC_OK;
+}
+
 int autotune_2d(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out) {
   Plan2D* pl = h->p2;
   const int prec = h->p.prec;
@@ -958,7 +982,7 @@ int autotune_2d(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t
         rc = plan2d_set_tile(pl, c);
         if (rc != RIDC_OK) return rc;
         double us = 0;
-        rc = plan2d_time_step(pl, s, 10, h->stream, &us);
+        rc = time_2d_steps(pl, s, 10, h->stream, &us);
         if (rc != RIDC_OK) return rc;
         if (us < best) {
           best = us;

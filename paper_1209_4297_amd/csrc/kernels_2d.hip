@@ -1691,29 +1691,6 @@ int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, do
   return RIDC_OK;
 }
 
-int plan2d_time_step(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us) {
-  // a step reads only ring slots that none of its stages writes (the level rings hold the
-  // window each level still reads, apart from the slot being written), so every run
-  // recomputes the same values
-  run_stages(pl->prec, pl->d_levels, pl->d_passes, pl->P, pl->n, sigma, pl->tile, stream);
-  hipEvent_t a, b;
-  RIDC_HIP_TRY(hipEventCreate(&a));
-  RIDC_HIP_TRY(hipEventCreate(&b));
-  (void)hipEventRecord(a, stream);
-  for (int r = 0; r < reps; ++r)
-    run_stages(pl->prec, pl->d_levels, pl->d_passes, pl->P, pl->n, sigma, pl->tile, stream);
-  (void)hipEventRecord(b, stream);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipEventSynchronize(b);
-  float ms = 0;
-  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
-  if (e != hipSuccess) return fail(RIDC_E_HIP, std::string("step timing: ") + hipGetErrorString(e));
-  *us = 1e3 * (double)ms / reps;
-  return RIDC_OK;
-}
-
 int plan2d_time_rhs(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us,
                     double* bytes) {
   const int P = pl->P;

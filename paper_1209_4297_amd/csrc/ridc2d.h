@@ -41,9 +41,6 @@ int plan2d_set_tile(Plan2D* pl, int tile);
 // `sigma` (every level active; the kind of most passes of a step), after computing that step's
 // right-hand side and first pass once.
 int plan2d_time_pass(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us);
-// Average duration (us) of `reps` back-to-back runs of every stage of step `sigma` (every level
-// active): what the plan's launch shape costs a step.  Each run recomputes the same values.
-int plan2d_time_step(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us);
 // Average duration (us) of `reps` back-to-back launches of the right-hand-side kernel of step
 // `sigma` (every level active) and its algorithmic HBM bytes per launch.
 int plan2d_time_rhs(Plan2D* pl, int64_t sigma, int reps, hipStream_t stream, double* us,
