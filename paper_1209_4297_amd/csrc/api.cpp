@@ -934,8 +934,8 @@ int advance_imex(const std::vector<ridc_handle*>& hs, int64_t max_steps, hipStre
 
 // 2D: the transform-pass shape of the handle's (n, precision), from the tuning table or
 // measured: every shape the plan allows times 10 whole steps with every level active (on zeroed
-// rings; a shape can change the first pass of a solve and the later ones differently), the
-// fastest is kept and recorded.  Leaves the handle unarmed.  Outputs:
+// rings; a shape can change the first pass of a solve and the later ones differently), best of
+// three rounds; the fastest is kept and recorded.  Leaves the handle unarmed.  Outputs:
 // threads per block of the chosen shape, 0, and the shape bits.
 // Average duration (us) of `reps` consecutive whole steps (every stage) of one plan from step s.
 int time_2d_steps(Plan2D* pl, int64_t s, int reps, hipStream_t stream, double* us) {
@@ -977,18 +977,22 @@ int autotune_2d(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t
       int rc = plan2d_arm(pl, (int64_t)1 << 30, h->stream);
       if (rc != RIDC_OK) return rc;
       const int64_t s = (int64_t)h->P * (h->P - 1) / 2 + 1;   // every level active
-      double best = 1e300;
-      for (int c : cands) {
-        rc = plan2d_set_tile(pl, c);
-        if (rc != RIDC_OK) return rc;
-        double us = 0;
-        rc = time_2d_steps(pl, s, 10, h->stream, &us);
-        if (rc != RIDC_OK) return rc;
-        if (us < best) {
-          best = us;
-          tile = c;
+      // three interleaved rounds, each candidate's best round counts (shapes within a few
+      // per cent of each other would otherwise trade places with the run-to-run spread)
+      std::vector<double> t(cands.size(), 1e300);
+      for (int round = 0; round < 3; ++round)
+        for (size_t i = 0; i < cands.size(); ++i) {
+          rc = plan2d_set_tile(pl, cands[i]);
+          if (rc != RIDC_OK) return rc;
+          double us = 0;
+          rc = time_2d_steps(pl, s, 10, h->stream, &us);
+          if (rc != RIDC_OK) return rc;
+          t[i] = std::min(t[i], us);
         }
-      }
+      size_t bi = 0;
+      for (size_t i = 1; i < cands.size(); ++i)
+        if (t[i] < t[bi]) bi = i;
+      tile = cands[bi];
     }
     tune_put_2d(h->p.n, prec, tile);
     int rc = plan2d_set_tile(pl, tile);
