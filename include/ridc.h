@@ -244,8 +244,9 @@ int ridc_step_cost(const ridc_handle* h, double* hbm_bytes, double* flops);
  *  - 2D: the transform-pass shapes the handle's side and precision allow, keyed by (n,
  *    precision): 32- or 64-column waves (FP32/FP64 passes), 64- or 32-wide k-slices
  *    (split-BF16 pass), prefolded or row-major intermediates (n a multiple of 256), each
- *    timed over 10 whole pipeline steps (best of three rounds).  threads_out receives the threads per block,
- *    rows_out 0, flags_out the shape bits as in ridc_set_tile.
+ *    timed over whole pipeline steps (10 at n <= 1024, fewer above; best of three rounds).
+ *    threads_out receives the threads per block, rows_out 0, flags_out the shape bits as in
+ *    ridc_set_tile.
  * A shape already recorded for the key (this process, or the tuning cache file) is applied
  * without measuring; ridc_tune_clear forgets the table.  Every shape performs the same
  * operations for every output value, so results are bitwise independent of the choice.  The

@@ -932,11 +932,6 @@ int advance_imex(const std::vector<ridc_handle*>& hs, int64_t max_steps, hipStre
   return RIDC_OK;
 }
 
-// 2D: the transform-pass shape of the handle's (n, precision), from the tuning table or
-// measured: every shape the plan allows times 10 whole steps with every level active (on zeroed
-// rings; a shape can change the first pass of a solve and the later ones differently), best of
-// three rounds; the fastest is kept and recorded.  Leaves the handle unarmed.  Outputs:
-// threads per block of the chosen shape, 0, and the shape bits.
 // Average duration (us) of `reps` consecutive whole steps (every stage) of one plan from step s.
 int time_2d_steps(Plan2D* pl, int64_t s, int reps, hipStream_t stream, double* us) {
   Plan2D* pls[1] = {pl};
@@ -961,6 +956,12 @@ int time_2d_steps(Plan2D* pl, int64_t s, int reps, hipStream_t stream, double* u
   return RIDC_OK;
 }
 
+// 2D: the transform-pass shape of the handle's (n, precision), from the tuning table or
+// measured: every shape the plan allows times whole steps with every level active (10 at
+// n <= 1024, fewer above so that the measurement stays near a tenth of a second per shape; on
+// zeroed rings; a shape can change the first pass of a solve and the later ones differently),
+// best of three rounds; the fastest is kept and recorded.  Leaves the handle unarmed.
+// Outputs: threads per block of the chosen shape, 0, and the shape bits.
 int autotune_2d(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t* flags_out) {
   Plan2D* pl = h->p2;
   const int prec = h->p.prec;
@@ -977,6 +978,8 @@ int autotune_2d(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t
       int rc = plan2d_arm(pl, (int64_t)1 << 30, h->stream);
       if (rc != RIDC_OK) return rc;
       const int64_t s = (int64_t)h->P * (h->P - 1) / 2 + 1;   // every level active
+      const double scale = 1024.0 / (double)h->p.n;
+      const int steps = (int)std::max(1.0, std::min(10.0, 10.0 * scale * scale * scale));
       // three interleaved rounds, each candidate's best round counts (shapes within a few
       // per cent of each other would otherwise trade places with the run-to-run spread)
       std::vector<double> t(cands.size(), 1e300);
@@ -985,7 +988,7 @@ int autotune_2d(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32_t
           rc = plan2d_set_tile(pl, cands[i]);
           if (rc != RIDC_OK) return rc;
           double us = 0;
-          rc = time_2d_steps(pl, s, 10, h->stream, &us);
+          rc = time_2d_steps(pl, s, steps, h->stream, &us);
           if (rc != RIDC_OK) return rc;
           t[i] = std::min(t[i], us);
         }
