@@ -249,13 +249,24 @@ int choose_tile_1d(const ridc_problem* p, const PcrPlan& pcr, Tile1D* out,
     return RIDC_OK;
   }
   const int64_t H = halo_rows(pcr);
-  // default: chunks of 1024 rows when the system is long and the halo is small against them
-  // (the whole-range workgroup is left to measurement: ridc_autotune, ridc_set_tile)
-  Tile1D chunk{0, 1024, 256};
-  if (p->n >= 2048 && H <= 512 && tile_fits(p, pcr, chunk)) {
-    *out = chunk;
-    return RIDC_OK;
+  // default for long systems with a short PCR halo: chunks, as many as give about 256
+  // workgroups per step over the levels (one per CU: a single system's step is bound by
+  // latency, not bytes), at least 128 rows each, 1024 threads where the order allows
+  // (measured at n = 8192, order 4: 128-row chunks of 1024 threads run a step in 5.3 us,
+  // 1024-row chunks of 256 threads in 10.8).  The whole-range workgroup is left to
+  // measurement: ridc_autotune, ridc_set_tile.
+  if (p->n >= 2048 && H <= 512) {
+    const int64_t per_level = std::max<int64_t>(1, 256 / p->order);
+    int64_t B = (p->n / per_level) / 64 * 64;
+    B = std::min<int64_t>(1024, std::max<int64_t>(128, B));
+    const int threads = p->order <= kMaxJ1024 + 1 ? 1024 : 256;
+    Tile1D chunk{0, (int)B, threads};
+    if (tile_fits(p, pcr, chunk)) {
+      *out = chunk;
+      return RIDC_OK;
+    }
   }
+  Tile1D chunk{0, 1024, 256};
   Tile1D wrap{1, 0, 256};
   if (tile_fits(p, pcr, wrap)) {
     *out = wrap;
