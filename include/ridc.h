@@ -257,8 +257,9 @@ int ridc_autotune(ridc_handle* h, int32_t* threads_out, int32_t* rows_out, int32
 /* 2D handles: set the transform-pass shape bits `flags` (1: 64-column waves, FP32/FP64 passes
  * with n/2 a multiple of 64 or no fold; 2: 32-wide k-slices, split-BF16 pass; 4: row-major
  * intermediates folded while staging, instead of the folded planes (sums and differences of
- * mirrored columns) that the passes exchange by default when n is a multiple of 256; 0: the
- * default); rows must be 0 and threads is ignored; results do not depend on the shape.
+ * mirrored columns) that the passes exchange by default when n is a multiple of 256; 0: none
+ * of these).  A handle with no recorded shape starts at 0, split-BF16 handles at 2 where 2 is
+ * allowed.  rows must be 0 and threads is ignored; results do not depend on the shape.
  * 1D: force a tiling: threads in {64,128,256,512,1024}; rows = 0 for the whole cycle in one
  * workgroup, else chunks of `rows` rows (allowed when the PCR coupling vanishes within a halo
  * shorter than the system); flags bit 0 = write level values with nontemporal stores; flags

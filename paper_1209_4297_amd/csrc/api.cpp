@@ -1178,6 +1178,15 @@ int ridc_create(const ridc_problem* p, void* hip_stream, ridc_handle** out) {
       ridc_destroy(h);
       return rc;
     }
+    // untuned split-BF16 plans take the 32-wide k-slices for the first pass of a solve where
+    // they are a choice (whole steps at n = 1024: 229-232 against 233-239 us)
+    int tuned = 0;
+    if (p->prec == RIDC_PREC_BF16X3_REFINE && !tune_get_2d(p->n, p->prec, &tuned)) {
+      std::vector<int> c;
+      plan2d_tile_candidates(h->p2, &c);
+      if (std::find(c.begin(), c.end(), kPassNarrowK) != c.end())
+        (void)plan2d_set_tile(h->p2, kPassNarrowK);
+    }
   }
   *out = h;
   return RIDC_OK;

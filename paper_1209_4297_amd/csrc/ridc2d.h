@@ -33,7 +33,7 @@ constexpr int kPassWide64 = 1;
 constexpr int kPassNarrowK = 2;
 constexpr int kPassPlainA = 4;
 int plan2d_tile(const Plan2D* pl);
-// The shapes this plan's side and precision allow (0, the default, first).
+// The shapes this plan's side and precision allow (0 first).
 void plan2d_tile_candidates(const Plan2D* pl, std::vector<int>* out);
 // Errors: RIDC_E_INVAL for a shape the plan does not allow.
 int plan2d_set_tile(Plan2D* pl, int tile);
