@@ -180,18 +180,6 @@ __device__ __forceinline__ bool stencil_tile(int n, const StBlock& b, int* iy0, 
   return *ix0 < n && *iy0 < n;
 }
 
-// Column neighbours of a row value held one per lane: from the adjacent lanes, and for lanes 0
-// and 63 from `edge(column)` (zero outside the grid).
-template <typename T, typename Edge>
-__device__ __forceinline__ void column_neighbours(T mid, int ix0, int n, Edge edge, double* w,
-                                                  double* e) {
-  const int lane = threadIdx.x & 63;
-  *w = (double)lane_below(mid);
-  *e = (double)lane_above(mid);
-  if (lane == 0 && ix0 > 0) *w = (double)edge(ix0 - 1);
-  if (lane == 63 && ix0 + 64 < n) *e = (double)edge(ix0 + 64);
-}
-
 // ---------------------------------------------------------------------------------------------
 // right-hand side (increment form), FP64; also writes the low-precision copy.  The quadrature
 // of f along level j-1 is taken as sum_i w_i f_E(v_i) + nu Lap_h (sum_i w_i v_i): the stencil
@@ -245,51 +233,75 @@ __device__ __forceinline__ void rhs_level(const Lvl2D& L, int64_t m, int iy0, in
       if (i < nv) V += w[i] * vp[i][c];
     return V;
   };
+  // The walk down the strip goes RG rows at a time, each group unrolled and without a branch,
+  // so that the loads of a group's rows are issued together: lanes past n and rows outside the
+  // grid load a clamped in-range address and take zero instead, lanes 0 and 63 take their edge
+  // column by a select, and the stores follow each group.  Every wave has ST_RY rows (n is a
+  // multiple of 32).  Measured at 1024^2, FP64: 29.1 us per launch with a branch per row and
+  // edge, 22.6 us with RG = 2 (114 registers), 22.8 with 1, 26.5 with 4 (148), 27.7 with 8
+  // (228), 38.5 with the whole strip unrolled (388 registers, one wave per SIMD).
+  const int ixc = col ? ix : n - 1;
   auto load = [&](int iy) {
+    const bool in = iy >= 0 && iy < n && col;
+    const int64_t c = (int64_t)(iy < 0 ? 0 : (iy < n ? iy : n - 1)) * n + ixc;
     RhsRow r{0.0, 0.0, 0.0, 0.0, 0.0};
-    if (iy < 0 || iy >= n || !col) return r;
-    const int64_t c = (int64_t)iy * n + ix;
     if (JT == 0) {
       r.u = u[c];
       r.V = r.u;
       r.fq = fe2(L.fe, r.u);
-      return r;
-    }
-    r.u = u[c];
+    } else {
+      r.u = u[c];
 #pragma unroll
-    for (int i = 0; i < JN; ++i) {
-      if (i < nv) {
-        const double v = vp[i][c];
-        const double f = fe2(L.fe, v);
-        r.V += w[i] * v;
-        r.fq += w[i] * f;
-        if (i == rn) r.fen = f;
-        if (i == rn + 1) r.vn1 = v;
+      for (int i = 0; i < JN; ++i) {
+        if (i < nv) {
+          const double v = vp[i][c];
+          const double f = fe2(L.fe, v);
+          r.V += w[i] * v;
+          r.fq += w[i] * f;
+          if (i == rn) r.fen = f;
+          if (i == rn + 1) r.vn1 = v;
+        }
       }
     }
-    return r;
+    const RhsRow z{0.0, 0.0, 0.0, 0.0, 0.0};
+    return in ? r : z;
   };
+  // the column just outside the strip that lane 0 (west) or lane 63 (east) takes: every lane
+  // of a half reads that one address (zero outside the grid, the Dirichlet ghost value)
+  const int lane = threadIdx.x & 63;
+  const int xo = lane < 32 ? ix0 - 1 : ix0 + 64;
+  const bool xok = xo >= 0 && xo < n;
+  const int xoc = xok ? xo : ixc;
   const double dt = L.dt;
   double up = load(iy0 - 1).V;
   RhsRow mid = load(iy0);
-  const int rows = n - iy0 < ST_RY ? n - iy0 : ST_RY;
-  for (int r = 0; r < rows; ++r) {
-    const int iy = iy0 + r;
-    const RhsRow dn = load(iy + 1);
-    double vw, ve;
-    column_neighbours(mid.V, ix0, n, [&](int x) { return window_sum((int64_t)iy * n + x); }, &vw,
-                      &ve);
-    const double lap = ((vw + ve) + (up + dn.V)) - 4.0 * mid.V;
-    const double quad = mid.fq + L.nu_h2 * lap;
-    const double b = JT == 0 ? dt * quad
-                             : (mid.u - mid.vn1) + dt * quad + dt * (fe2(L.fe, mid.u) - mid.fen);
-    if (col) {
-      const int64_t c = (int64_t)iy * n + ix;
-      L.b64[c] = b;
-      if (L.prec != PREC_F64) store_lo(L.lo0, c, b);
+  constexpr int RG = 2;
+#pragma unroll
+  for (int q = 0; q < ST_RY; q += RG) {
+    double bs[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      const int iy = iy0 + q + r;
+      const RhsRow dn = load(iy + 1);
+      const double ev = window_sum((int64_t)iy * n + xoc);
+      double vw = lane_below(mid.V), ve = lane_above(mid.V);
+      vw = lane == 0 ? (xok ? ev : 0.0) : vw;
+      ve = lane == 63 ? (xok ? ev : 0.0) : ve;
+      const double lap = ((vw + ve) + (up + dn.V)) - 4.0 * mid.V;
+      const double quad = mid.fq + L.nu_h2 * lap;
+      bs[r] = JT == 0 ? dt * quad
+                      : (mid.u - mid.vn1) + dt * quad + dt * (fe2(L.fe, mid.u) - mid.fen);
+      up = mid.V;
+      mid = dn;
     }
-    up = mid.V;
-    mid = dn;
+    if (col) {
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        const int64_t c = (int64_t)(iy0 + q + r) * n + ix;
+        L.b64[c] = bs[r];
+        if (L.prec != PREC_F64) store_lo(L.lo0, c, bs[r]);
+      }
+    }
   }
 }
 
