@@ -48,19 +48,36 @@ MEASURED_TRAFFIC = {
     ("reacdiff1d", (1024, 128, 0)): ("1d", "7487c6781845e08d", 4530176),
     ("batched1d", (256, 1536)): ("1d", "7487c6781845e08d", 72678016),
     ("batched1d", (512, 1536)): ("1d", "7487c6781845e08d", 72604672),
-    ("reacdiff2d_rhs", "fp64"): ("2d", "5c7ce28bfb41124f", 148963968),
-    ("reacdiff2d_rhs", "fp32"): ("2d", "5c7ce28bfb41124f", 166499456),
-    ("reacdiff2d_rhs", "bf16x3"): ("2d", "5c7ce28bfb41124f", 166430848),
+    ("reacdiff2d_rhs", "fp64"): ("2d", "c5e33ed3350678dd", 148489472),
+    ("reacdiff2d_rhs", "fp32"): ("2d", "c5e33ed3350678dd", 167123712),
+    ("reacdiff2d_rhs", "bf16x3"): ("2d", "c5e33ed3350678dd", 167306240),
     # the timed transform pass (the second of a step) per (precision, pass-shape bits)
-    ("reacdiff2d", ("fp64", 0)): ("2d", "5c7ce28bfb41124f", 100898816),
-    ("reacdiff2d", ("fp64", 4)): ("2d", "5c7ce28bfb41124f", 100904192),
-    ("reacdiff2d", ("fp32", 0)): ("2d", "5c7ce28bfb41124f", 50555648),
-    ("reacdiff2d", ("fp32", 4)): ("2d", "5c7ce28bfb41124f", 50574080),
-    ("reacdiff2d", ("bf16x3", 0)): ("2d", "5c7ce28bfb41124f", 50557696),
+    ("reacdiff2d", ("fp64", 0)): ("2d", "c5e33ed3350678dd", 100894720),
+    ("reacdiff2d", ("fp64", 4)): ("2d", "c5e33ed3350678dd", 100911360),
+    ("reacdiff2d", ("fp32", 0)): ("2d", "c5e33ed3350678dd", 50540288),
+    ("reacdiff2d", ("fp32", 4)): ("2d", "c5e33ed3350678dd", 50563840),
+    ("reacdiff2d", ("bf16x3", 0)): ("2d", "c5e33ed3350678dd", 50557696),
     # bit 2 reshapes only the first pass of each solve: the timed pass is the same kernel
-    ("reacdiff2d", ("bf16x3", 2)): ("2d", "5c7ce28bfb41124f", 50557696),
-    ("reacdiff2d", ("bf16x3", 4)): ("2d", "5c7ce28bfb41124f", 50548480),
+    ("reacdiff2d", ("bf16x3", 2)): ("2d", "c5e33ed3350678dd", 50557696),
+    ("reacdiff2d", ("bf16x3", 4)): ("2d", "c5e33ed3350678dd", 50563840),
 }
+
+
+def hbm_roofline(kernel, us, own, method):
+    """HBM roofline of one launch: `own` is what the kernel must move at this step (every stored
+    value it reads, once, and every vector it writes; it recomputes f instead of storing it),
+    `method` the count for the method with stored f windows (method_step_bytes).  The kernel
+    does not move the difference, so only `own` is a fraction of the HBM peak; the method's
+    rate is a labelled extra and can exceed the peak."""
+    ach = own / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": kernel,
+            "launch_us": round(us, 3), "bytes_per_launch": own,
+            "method_bytes_per_launch": method,
+            "method_equivalent_gbs": round(method / (us * 1e-6) / 1e9, 2),
+            "note": "achieved counts the bytes the kernel must move (stored values read once, "
+                    "vectors written; f recomputed); method_equivalent_gbs counts the method's "
+                    "stored-window bytes per unknown-step, which are not moved"}
 
 
 def method_step_bytes(P, unknowns):
@@ -70,7 +87,7 @@ def method_step_bytes(P, unknowns):
     value, the j+1 F of its window and one C, and writes value, F and C; the top level reads P+2
     vectors and writes its value.  That is 2, 9, 17, 26 vectors per unknown for orders 1-4
     (16, 72, 136, 208 B).  The kernels keep only the values and recompute f from them, so they
-    move fewer bytes than this count (kernel_bytes_per_launch)."""
+    move fewer bytes than this count (hbm_roofline)."""
     if P == 1:
         vectors = 2
     else:
@@ -209,15 +226,7 @@ def roofline_single(ridc, s, x0, nt, reps, bound, prec):
     us, work = s.kernel_time(reps)
     s.sync()
     if bound == "hbm":
-        alg = method_step_bytes(P, s.side)
-        ach = alg / (us * 1e-6) / 1e9
-        return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_step1d",
-                "launch_us": round(us, 3), "bytes_per_launch": alg,
-                "kernel_bytes_per_launch": work,
-                "kernel_frac": round(work / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
-                "note": "achieved counts the method's stored-window bytes per unknown-step; the "
-                        "kernel recomputes f and moves kernel_bytes_per_launch"}
+        return hbm_roofline("k_step1d", us, work, method_step_bytes(P, s.side))
     return roofline_pass(us, work, s.side, prec)
 
 
@@ -449,15 +458,7 @@ def stencil_roofline(ridc, s, x0, nt, reps):
     ridc.advance([s], P * (P - 1) // 2)
     us, kbytes = s.stencil_time(reps)
     s.sync()
-    alg = method_step_bytes(P, n * n)
-    ach = alg / (us * 1e-6) / 1e9
-    return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
-            "kernel": "k_rhs2d", "launch_us": round(us, 3), "bytes_per_launch": alg,
-            "kernel_bytes_per_launch": kbytes,
-            "kernel_frac": round(kbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
-            "note": "achieved counts the method's stored-window bytes per unknown-step; the "
-                    "kernel recomputes f and moves kernel_bytes_per_launch"}
+    return hbm_roofline("k_rhs2d", us, kbytes, method_step_bytes(P, n * n))
 
 
 def bench_2d(args, torch, ridc):
@@ -582,14 +583,7 @@ def bench_batched(args, torch, ridc):
     ridc.advance(solvers, 6)
     us, bytes_per = ridc.batch_kernel_time(solvers, args.reps)
     alg = sum(method_step_bytes(p["order"], p["n"]) for p, _ in cases)
-    ach = alg / (us * 1e-6) / 1e9
-    roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_step1d (grouped)",
-            "launch_us": round(us, 3), "bytes_per_launch": alg,
-            "kernel_bytes_per_launch": bytes_per,
-            "kernel_frac": round(bytes_per / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
-            "note": "achieved counts the method's stored-window bytes per unknown-step; the "
-                    "kernel recomputes f and moves kernel_bytes_per_launch"}
+    roof = hbm_roofline("k_step1d (grouped)", us, bytes_per, alg)
     traffic = measured_traffic("batched1d", batch_tile)
     if traffic is not None and args.nt is None:
         roof["traffic"] = traffic
