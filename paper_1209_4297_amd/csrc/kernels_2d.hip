@@ -337,33 +337,44 @@ __global__ __launch_bounds__(256) void k_resid2d(const Lvl2D* __restrict__ level
   const int ix = ix0 + lane;
   const bool col = ix < n;
   const float* __restrict__ x1 = (const float*)L.x64;
-  // the column just outside the strip that lanes 0 and 63 supply, if it is inside the grid
-  const int ex = lane == 0 ? ix0 - 1 : ix0 + 64;
-  const bool edge = (lane == 0 && ix0 > 0) || (lane == 63 && ix0 + 64 < n);
+  // No load sits behind a branch, so that all of them issue back to back: lanes past n and the
+  // rows beyond the grid read a clamped in-range address and take zero instead, and the column
+  // just outside the strip, which lane 0 (west) or 63 (east) takes, is read by every lane of
+  // its half at that one address.  Every wave has ST_RY rows (n is a multiple of 32).
+  const int ixc = col ? ix : n - 1;
+  const int xo = lane < 32 ? ix0 - 1 : ix0 + 64;
+  const bool xok = xo >= 0 && xo < n;
+  const int xoc = xok ? xo : ixc;
   float xr[ST_RY + 2], xe[ST_RY];
   double br[ST_RY];
 #pragma unroll
   for (int r = 0; r < ST_RY + 2; ++r) {
     const int iy = iy0 - 1 + r;
-    xr[r] = iy >= 0 && iy < n && col ? gld<float>(x1 + (int64_t)iy * n + ix) : 0.0f;
+    const int iyc = iy < 0 ? 0 : (iy < n ? iy : n - 1);
+    const float v = gld<float>(x1 + (int64_t)iyc * n + ixc);
+    xr[r] = iy >= 0 && iy < n && col ? v : 0.0f;
   }
 #pragma unroll
   for (int r = 0; r < ST_RY; ++r) {
-    const int iy = iy0 + r;
-    const bool in = iy < n;
-    br[r] = in && col ? gld<double>(L.b64 + (int64_t)iy * n + ix) : 0.0;
-    xe[r] = in && edge ? gld<float>(x1 + (int64_t)iy * n + ex) : 0.0f;
+    const int64_t row = (int64_t)(iy0 + r) * n;
+    const double b = gld<double>(L.b64 + row + ixc);
+    const float e = gld<float>(x1 + row + xoc);
+    br[r] = col ? b : 0.0;
+    xe[r] = xok ? e : 0.0f;
   }
+  double res[ST_RY];
 #pragma unroll
   for (int r = 0; r < ST_RY; ++r) {
-    const int iy = iy0 + r;
-    if (iy >= n) break;
     double xw = (double)lane_below(xr[r + 1]), xa = (double)lane_above(xr[r + 1]);
-    if (lane == 0) xw = (double)xe[r];
-    if (lane == 63) xa = (double)xe[r];
+    xw = lane == 0 ? (double)xe[r] : xw;
+    xa = lane == 63 ? (double)xe[r] : xa;
     const double x = (double)xr[r + 1];
     const double lap = ((xw + xa) + ((double)xr[r] + (double)xr[r + 2])) - 4.0 * x;
-    if (col) store_lo(L.lo0, (int64_t)iy * n + ix, br[r] - (x - L.dt * L.nu_h2 * lap));
+    res[r] = br[r] - (x - L.dt * L.nu_h2 * lap);
+  }
+  if (col) {
+#pragma unroll
+    for (int r = 0; r < ST_RY; ++r) store_lo(L.lo0, (int64_t)(iy0 + r) * n + ix, res[r]);
   }
 }
 
