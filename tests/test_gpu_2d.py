@@ -97,6 +97,33 @@ def test_mixed_precision_parity(env, prec, n, nt):
         assert err <= tol_of(prec, j) and emax <= tol_of(prec, j), (j, err, emax)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_kernel_time_leaves_the_integration_unchanged(env, prec):
+    """ridc_kernel_time runs the next step's stages again and again around its timed pass; the
+    level rings and the handle's position must come out as they went in, so an integration
+    timed half-way ends bitwise where an untimed one does."""
+    torch, ridc = env
+    prob, u0 = workloads.config_reacdiff_2d(n=256, nt=12, order=4, T=0.024, nu=1e-3)
+    _say(f"case: 2D {prec} kernel_time mid-integration")
+    x0 = torch.tensor(u0.reshape(-1), device="cuda")
+
+    def run(timed):
+        s = ridc.Ridc(prob, prec=prec)
+        s.begin(x0, prob["nt"])
+        ridc.advance([s], 8)
+        if timed:
+            us, flops = s.kernel_time(3)
+            assert us > 0 and flops > 0
+        ridc.advance([s], s.remaining())
+        uT = torch.empty_like(x0)
+        s.read(uT)
+        s.sync()
+        s.close()
+        return uT.cpu().numpy()
+
+    assert np.array_equal(run(True), run(False))
+
+
 def test_largest_side_sine_mode_closed_form(env):
     """n = 16384, the largest 2D side (a vector is 2 GiB, so every address is 64-bit).  With no
     explicit term a discrete sine mode is an eigenvector of the 5-point Laplacian, and order 1
