@@ -133,9 +133,10 @@ __device__ __forceinline__ void store_lo(void* base, int64_t idx, double v) {
 // ---------------------------------------------------------------------------------------------
 // stencil kernels: a wave owns 64 columns of ST_RY consecutive rows and walks down them, keeping
 // the rows above and below in registers, so each stencil vector is read once per point.  Column
-// neighbours come from the adjacent lanes (DPP wave shifts); lanes 0 and 63 load the columns
-// just outside the wave's 64.  Columns at or beyond n hold zero, which is also the Dirichlet
-// ghost value, so a wave that straddles the last column needs no special case.
+// neighbours come from the adjacent lanes (DPP wave shifts); the columns just outside the wave's
+// 64, which lanes 0 and 63 take, come from one load per half-wave at one address.  Columns at or
+// beyond n hold zero, which is also the Dirichlet ghost value, so a wave that straddles the last
+// column needs no special case.
 // ---------------------------------------------------------------------------------------------
 constexpr int ST_RY = 16;    // rows per wave
 constexpr int ST_WAVES = 4;  // waves per block, stacked in rows
