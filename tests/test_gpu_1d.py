@@ -81,8 +81,17 @@ def test_reacdiff_n8192_full(env):
 
 
 def test_reacdiff_chunked_ragged(env):
-    # n = 3000 with r = 4.5: few PCR stages, so chunks of 1024 rows (ragged last chunk)
+    # n = 3000 with r = 4.5: few PCR stages, so the default tiling cuts it into chunks (128
+    # rows, the last one ragged)
     prob, u0 = workloads.config_reacdiff_1d(n=3000, nt=400, T=0.2)
+    check_against_oracle(env, prob, u0)
+
+
+@pytest.mark.parametrize("order", [6, 8])
+def test_long_system_default_tiling_high_orders(env, order):
+    # orders 6 and 8 on a chunked system: the default tiling takes 1024 threads up to order 6
+    # and 256 above, with chunks of at least 128 rows
+    prob, u0 = workloads.config_reacdiff_1d(n=2304, nt=24, order=order, T=0.012)
     check_against_oracle(env, prob, u0)
 
 
